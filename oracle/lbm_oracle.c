@@ -1,0 +1,499 @@
+/*
+ * lbm_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow FP64 CPU implementation of the incompressible 14- and
+ * 18-velocity multiple-relaxation-time lattice Boltzmann step of
+ * Zhang, Shi & Wang, "14-velocity and 18-velocity multiple-relaxation-time
+ * lattice Boltzmann models for three-dimensional incompressible flows"
+ * (arXiv 1503.03337).  It exists so that the GPU library can be checked
+ * against something written straight from the paper.  Only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never calls it, and it shares no code, table or header with
+ * the HIP library.
+ *
+ * What is followed, and where:
+ *   velocity sets ........ Sec. 3 (iD3Q14) and Appendix B (iD3Q18)
+ *   weights .............. Eq. (omega) for the D3Q19 lattice (Appendix B);
+ *                          for the 14-velocity model the D3Q15 weights
+ *                          2/9, 1/9, 1/72 (the printed Eq. (omega) lists the
+ *                          D3Q19 values; only the D3Q15 ones reproduce the
+ *                          printed moment equilibria Eq. (meq) via T f_eq)
+ *   equilibrium .......... Eqs. (edf), (lamda_alpha)
+ *   p, u recovery ........ Eq. (hgl), with u = sum c f + F/2 when a body
+ *                          force F acts (forcing is not in the paper: the
+ *                          moment-space Guo form m_F = (d m_eq / d u) . F
+ *                          is used, so F = 0 gives the paper's scheme)
+ *   transform T .......... Eq. (T14) and the 18x18 T of Appendix B,
+ *                          typed in as printed
+ *   moment equilibria .... Eq. (meq) (Sec. 3) and Appendix B
+ *   relaxation ........... Eq. (mrteqvT) with the diagonal of
+ *                          Eqs. (sD3Q15) / (sD3Q19)
+ *   T^-1 ................. T T' is diagonal (rows mutually orthogonal,
+ *                          Sec. 3), so T^-1 = T' N^-1 with N_k the squared
+ *                          row norms, computed here from T
+ *   streaming + walls .... Eq. (mrteq) for the free flight; walls are
+ *                          half-way bounce-back with the moving-wall term
+ *                          -2 w_a (c_a . u_w) / c_s^2 taken from the linear
+ *                          term of Eq. (edf) (the paper itself uses
+ *                          non-equilibrium extrapolation)
+ *
+ * Layout: f[a*N + n], n = x + nx*(y + ny*z), a = 0..q-1 in the paper's
+ * order 1..q.  Everything is FP64.  Build: -O2 -ffp-contract=off.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define QMAX 18
+
+/* ---- lattices (Sec. 3 for q = 14, Appendix B for q = 18) ------------- */
+static const int VEL14[14][3] = {
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},   {0, 0, 1},
+    {0, 0, -1}, {1, 1, 1},  {-1, 1, 1}, {1, -1, 1},   {-1, -1, 1},
+    {1, 1, -1}, {-1, 1, -1}, {1, -1, -1}, {-1, -1, -1}};
+
+static const int VEL18[18][3] = {
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0}, {1, 0, 1}, {-1, 0, 1},
+    {1, 0, -1}, {-1, 0, -1}, {0, 1, 1}, {0, -1, 1}, {0, 1, -1}, {0, -1, -1}};
+
+/* Eq. (T14), as printed. */
+static const int TMAT14[14][14] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -4, -4, -4, -4, -4, 3, 3, 3, 3, 3, 3, 3, 3},
+    {1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1},
+    {-4, 4, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1},
+    {0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},
+    {0, 0, -4, 4, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},
+    {0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1},
+    {0, 0, 0, 0, -4, 4, 1, 1, 1, 1, -1, -1, -1, -1},
+    {2, 2, -1, -1, -1, -1, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1},
+    {0, 0, 0, 0, 0, 0, 1, 1, -1, -1, -1, -1, 1, 1},
+    {0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, -1, 1},
+    {0, 0, 0, 0, 0, 0, 1, -1, -1, 1, -1, 1, 1, -1}};
+
+/* The 18x18 T of Appendix B, as printed. */
+static const int TMAT18[18][18] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-2, -2, -2, -2, -2, -2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0},
+    {-4, 4, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, -4, 4, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},
+    {0, 0, 0, 0, -4, 4, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},
+    {2, 2, -1, -1, -1, -1, 1, 1, 1, 1, 1, 1, 1, 1, -2, -2, -2, -2},
+    {-4, -4, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, -2, -2, -2, -2},
+    {0, 0, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0},
+    {0, 0, -2, -2, 2, 2, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, -1, 1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, -1, -1, -1, -1, 1, 1}};
+
+/* The lattice in use, with the derived quantities the step needs. */
+typedef struct {
+  int q;
+  int c[QMAX][3];
+  double w[QMAX]; /* w_1..w_q */
+  double w0;      /* weight of the dropped rest velocity */
+  int opp[QMAX];  /* index of -c_a */
+  int T[QMAX][QMAX];
+  double N[QMAX]; /* N_k = sum_a T_ka^2 */
+} lattice;
+
+static int make_lattice(int q, lattice* L) {
+  int a, b, k, d;
+  if (q != 14 && q != 18) return -1;
+  memset(L, 0, sizeof(*L));
+  L->q = q;
+  for (a = 0; a < q; ++a) {
+    int len2 = 0;
+    for (d = 0; d < 3; ++d) {
+      L->c[a][d] = (q == 14) ? VEL14[a][d] : VEL18[a][d];
+      len2 += L->c[a][d] * L->c[a][d];
+    }
+    if (q == 14)
+      L->w[a] = (len2 == 1) ? 1.0 / 9.0 : 1.0 / 72.0;
+    else
+      L->w[a] = (len2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+    for (b = 0; b < q; ++b) L->T[a][b] = (q == 14) ? TMAT14[a][b] : TMAT18[a][b];
+  }
+  L->w0 = (q == 14) ? 2.0 / 9.0 : 1.0 / 3.0;
+  for (a = 0; a < q; ++a) {
+    L->opp[a] = -1;
+    for (b = 0; b < q; ++b)
+      if (L->c[b][0] == -L->c[a][0] && L->c[b][1] == -L->c[a][1] &&
+          L->c[b][2] == -L->c[a][2])
+        L->opp[a] = b;
+    if (L->opp[a] < 0) return -1;
+  }
+  for (k = 0; k < q; ++k) {
+    int s = 0;
+    for (a = 0; a < q; ++a) s += L->T[k][a] * L->T[k][a];
+    L->N[k] = (double)s;
+  }
+  return 0;
+}
+
+/* ---- problem description (mirrored by a ctypes Structure) -------------- */
+typedef struct {
+  int q, nx, ny, nz;
+  double s[QMAX];        /* relaxation rates in the order of Eq. (moment) */
+  int face[6];           /* -x,+x,-y,+y,-z,+z: 0 periodic, 1 wall         */
+  double wall_u[6][3];   /* wall velocity of each wall face               */
+  double F0[3], FA[3];   /* body force F(t) = F0 + FA cos(2 pi t / FT)    */
+  double FT;             /* FT <= 0: constant force F0                    */
+} orc_problem;
+
+/* ---- single-node pieces ---------------------------------------------- */
+
+/* Eq. (edf) with Eq. (lamda_alpha) for a = 1..q (c_s^2 = 1/3). */
+static void feq_node(const lattice* L, double p, const double u[3], double* feq) {
+  int a;
+  double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (a = 0; a < L->q; ++a) {
+    double cu = L->c[a][0] * u[0] + L->c[a][1] * u[1] + L->c[a][2] * u[2];
+    double lam = L->w[a] * p * 3.0;
+    feq[a] = lam + L->w[a] * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+  }
+}
+
+/* Eq. (hgl): u = sum_a c_a f_a (+ F/2 under a body force),
+ * p = c_s^2/(1 - w0) [ sum_a f_a - w0 |u|^2 / (2 c_s^2) ]. */
+static void macro_node(const lattice* L, const double* f, const double F[3],
+                       double* p, double u[3]) {
+  int a, d;
+  double P = 0.0, j[3] = {0.0, 0.0, 0.0}, usq;
+  for (a = 0; a < L->q; ++a) {
+    P += f[a];
+    for (d = 0; d < 3; ++d) j[d] += L->c[a][d] * f[a];
+  }
+  for (d = 0; d < 3; ++d) u[d] = j[d] + 0.5 * F[d];
+  usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  *p = (P - 1.5 * L->w0 * usq) / (3.0 * (1.0 - L->w0));
+}
+
+/* Eq. (meq) for q = 14 (Sec. 3) and its Appendix B counterpart for q = 18. */
+static void meq_node(int q, double p, const double u[3], double* meq) {
+  double ux = u[0], uy = u[1], uz = u[2];
+  double usq = ux * ux + uy * uy + uz * uz;
+  if (q == 14) {
+    meq[0] = 7.0 * p / 3.0 + usq / 3.0;
+    meq[1] = -7.0 * p + usq;
+    meq[2] = ux;
+    meq[3] = -7.0 * ux / 3.0;
+    meq[4] = uy;
+    meq[5] = -7.0 * uy / 3.0;
+    meq[6] = uz;
+    meq[7] = -7.0 * uz / 3.0;
+    meq[8] = 3.0 * ux * ux - usq;
+    meq[9] = uy * uy - uz * uz;
+    meq[10] = ux * uy;
+    meq[11] = uy * uz;
+    meq[12] = ux * uz;
+    meq[13] = 0.0;
+  } else {
+    meq[0] = 2.0 * p + 0.5 * usq;
+    meq[1] = -p + 0.5 * usq;
+    meq[2] = ux;
+    meq[3] = -2.0 * ux / 3.0;
+    meq[4] = uy;
+    meq[5] = -2.0 * uy / 3.0;
+    meq[6] = uz;
+    meq[7] = -2.0 * uz / 3.0;
+    meq[8] = 3.0 * ux * ux - usq;
+    meq[9] = -0.5 * (3.0 * ux * ux - usq);
+    meq[10] = uy * uy - uz * uz;
+    meq[11] = -0.5 * (uy * uy - uz * uz);
+    meq[12] = ux * uy;
+    meq[13] = uy * uz;
+    meq[14] = ux * uz;
+    meq[15] = 0.0;
+    meq[16] = 0.0;
+    meq[17] = 0.0;
+  }
+}
+
+/* Forcing moments m_F = (d m_eq / d u) . F, p held fixed: the derivative of
+ * each line of meq_node.  (With F = 0 these vanish and the step is the
+ * paper's unforced scheme.) */
+static void mforce_node(int q, const double u[3], const double F[3], double* mF) {
+  double ux = u[0], uy = u[1], uz = u[2];
+  double Fx = F[0], Fy = F[1], Fz = F[2];
+  double w = ux * Fx + uy * Fy + uz * Fz; /* (1/2) d|u|^2 . F */
+  if (q == 14) {
+    mF[0] = 2.0 * w / 3.0;
+    mF[1] = 2.0 * w;
+    mF[2] = Fx;
+    mF[3] = -7.0 * Fx / 3.0;
+    mF[4] = Fy;
+    mF[5] = -7.0 * Fy / 3.0;
+    mF[6] = Fz;
+    mF[7] = -7.0 * Fz / 3.0;
+    mF[8] = 6.0 * ux * Fx - 2.0 * w;
+    mF[9] = 2.0 * (uy * Fy - uz * Fz);
+    mF[10] = ux * Fy + uy * Fx;
+    mF[11] = uy * Fz + uz * Fy;
+    mF[12] = ux * Fz + uz * Fx;
+    mF[13] = 0.0;
+  } else {
+    mF[0] = w;
+    mF[1] = w;
+    mF[2] = Fx;
+    mF[3] = -2.0 * Fx / 3.0;
+    mF[4] = Fy;
+    mF[5] = -2.0 * Fy / 3.0;
+    mF[6] = Fz;
+    mF[7] = -2.0 * Fz / 3.0;
+    mF[8] = 6.0 * ux * Fx - 2.0 * w;
+    mF[9] = -0.5 * (6.0 * ux * Fx - 2.0 * w);
+    mF[10] = 2.0 * (uy * Fy - uz * Fz);
+    mF[11] = -(uy * Fy - uz * Fz);
+    mF[12] = ux * Fy + uy * Fx;
+    mF[13] = uy * Fz + uz * Fy;
+    mF[14] = ux * Fz + uz * Fx;
+    mF[15] = 0.0;
+    mF[16] = 0.0;
+    mF[17] = 0.0;
+  }
+}
+
+/* One collision, Eq. (mrteqvT):
+ *   m = T f;  D_k = s_k (m_k - meq_k) - (1 - s_k/2) mF_k;
+ *   f*_a = f_a - sum_k T_ka D_k / N_k. */
+static void collide_node(const lattice* L, const double* s, const double* f,
+                         const double F[3], double* fstar) {
+  int a, k, q = L->q;
+  double p, u[3], m[QMAX], meq[QMAX], mF[QMAX], D[QMAX];
+  macro_node(L, f, F, &p, u);
+  for (k = 0; k < q; ++k) {
+    double acc = 0.0;
+    for (a = 0; a < q; ++a) acc += L->T[k][a] * f[a];
+    m[k] = acc;
+  }
+  meq_node(q, p, u, meq);
+  mforce_node(q, u, F, mF);
+  for (k = 0; k < q; ++k)
+    D[k] = s[k] * (m[k] - meq[k]) - (1.0 - 0.5 * s[k]) * mF[k];
+  for (a = 0; a < q; ++a) {
+    double acc = 0.0;
+    for (k = 0; k < q; ++k) acc += L->T[k][a] * (D[k] / L->N[k]);
+    fstar[a] = f[a] - acc;
+  }
+}
+
+static void force_at(const orc_problem* pr, long long t, double F[3]) {
+  int d;
+  double ph = 1.0;
+  if (pr->FT > 0.0) ph = cos(2.0 * M_PI * (double)t / pr->FT);
+  for (d = 0; d < 3; ++d) F[d] = pr->F0[d] + (pr->FT > 0.0 ? pr->FA[d] * ph : 0.0);
+}
+
+static int check_problem(const orc_problem* pr, lattice* L) {
+  int d;
+  if (make_lattice(pr->q, L)) return -1;
+  if (pr->nx < 1 || pr->ny < 1 || pr->nz < 1) return -1;
+  for (d = 0; d < 3; ++d)
+    if ((pr->face[2 * d] == 0) != (pr->face[2 * d + 1] == 0)) return -1;
+  return 0;
+}
+
+/* ---- the lattice step ------------------------------------------------ */
+
+/* Advance f_in (time level t) to f_out (t+1).  Every fluid node is
+ * collided, then each post-collision population either moves to x + c_a
+ * (periodic axes wrap) or, if x + c_a lies beyond a wall face, returns to x
+ * as the opposite population with the moving-wall term.  A link leaving
+ * through several wall faces takes the velocity of the z face it crosses,
+ * else the y face, else the x face. */
+static void step_impl(const orc_problem* pr, const lattice* L, long long t,
+                      const double* fin, double* fout) {
+  const int nx = pr->nx, ny = pr->ny, nz = pr->nz, q = L->q;
+  const size_t N = (size_t)nx * ny * nz;
+  double F[3];
+  int z;
+  force_at(pr, t, F);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+  for (z = 0; z < nz; ++z) {
+    int x, y, a, d;
+    double f[QMAX], fs[QMAX];
+    for (y = 0; y < ny; ++y)
+      for (x = 0; x < nx; ++x) {
+        const size_t n = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
+        for (a = 0; a < q; ++a) f[a] = fin[(size_t)a * N + n];
+        collide_node(L, pr->s, f, F, fs);
+        for (a = 0; a < q; ++a) {
+          int dst[3] = {x + L->c[a][0], y + L->c[a][1], z + L->c[a][2]};
+          int dim[3] = {nx, ny, nz};
+          int out[3] = {0, 0, 0}, outside = 0;
+          for (d = 0; d < 3; ++d) {
+            if (dst[d] >= 0 && dst[d] < dim[d]) continue;
+            if (pr->face[2 * d] == 0) {
+              dst[d] = (dst[d] + dim[d]) % dim[d];
+            } else {
+              out[d] = (dst[d] < 0) ? -1 : 1;
+              outside = 1;
+            }
+          }
+          if (!outside) {
+            size_t m = (size_t)dst[0] +
+                       (size_t)nx * ((size_t)dst[1] + (size_t)ny * dst[2]);
+            fout[(size_t)a * N + m] = fs[a];
+          } else {
+            const double* uw;
+            double cu;
+            if (out[2])
+              uw = pr->wall_u[out[2] < 0 ? 4 : 5];
+            else if (out[1])
+              uw = pr->wall_u[out[1] < 0 ? 2 : 3];
+            else
+              uw = pr->wall_u[out[0] < 0 ? 0 : 1];
+            cu = L->c[a][0] * uw[0] + L->c[a][1] * uw[1] + L->c[a][2] * uw[2];
+            fout[(size_t)L->opp[a] * N + n] = fs[a] - 6.0 * L->w[a] * cu;
+          }
+        }
+      }
+  }
+}
+
+/* ---- exported API (ctypes) ------------------------------------------- */
+
+int orc_lattice(int q, int* c, double* w, int* opp, double* w0, int* T, double* Nk) {
+  lattice L;
+  int a, k;
+  if (make_lattice(q, &L)) return -1;
+  for (a = 0; a < q; ++a) {
+    if (c) {
+      c[3 * a] = L.c[a][0];
+      c[3 * a + 1] = L.c[a][1];
+      c[3 * a + 2] = L.c[a][2];
+    }
+    if (w) w[a] = L.w[a];
+    if (opp) opp[a] = L.opp[a];
+    if (Nk) Nk[a] = L.N[a];
+    if (T)
+      for (k = 0; k < q; ++k) T[a * q + k] = L.T[a][k];
+  }
+  if (w0) *w0 = L.w0;
+  return 0;
+}
+
+int orc_feq(int q, double p, const double* u, double* feq) {
+  lattice L;
+  if (make_lattice(q, &L)) return -1;
+  feq_node(&L, p, u, feq);
+  return 0;
+}
+
+int orc_macro_node(int q, const double* f, const double* F, double* p, double* u) {
+  lattice L;
+  if (make_lattice(q, &L)) return -1;
+  macro_node(&L, f, F, p, u);
+  return 0;
+}
+
+int orc_meq(int q, double p, const double* u, double* meq) {
+  if (q != 14 && q != 18) return -1;
+  meq_node(q, p, u, meq);
+  return 0;
+}
+
+int orc_mforce(int q, const double* u, const double* F, double* mF) {
+  if (q != 14 && q != 18) return -1;
+  mforce_node(q, u, F, mF);
+  return 0;
+}
+
+int orc_collide(int q, const double* s, const double* f, const double* F, double* fstar) {
+  lattice L;
+  if (make_lattice(q, &L)) return -1;
+  collide_node(&L, s, f, F, fstar);
+  return 0;
+}
+
+/* Fill f (q x N) with f_eq(p(n), j(n)), j = u - F(t)/2, so that the
+ * velocity recovered at time t is u.  p/u may be NULL (then p0, u0). */
+int orc_init_eq(const orc_problem* pr, long long t, const double* p, const double* u,
+                double p0, const double* u0, double* f) {
+  lattice L;
+  size_t N, n;
+  double F[3];
+  int a;
+  if (check_problem(pr, &L)) return -1;
+  N = (size_t)pr->nx * pr->ny * pr->nz;
+  force_at(pr, t, F);
+  for (n = 0; n < N; ++n) {
+    double pn = p ? p[n] : p0, j[3], fe[QMAX];
+    int d;
+    for (d = 0; d < 3; ++d) j[d] = (u ? u[(size_t)d * N + n] : u0[d]) - 0.5 * F[d];
+    feq_node(&L, pn, j, fe);
+    for (a = 0; a < L.q; ++a) f[(size_t)a * N + n] = fe[a];
+  }
+  return 0;
+}
+
+/* Advance f (q x N, time level t0) by nsteps; result left in f. */
+int orc_run(const orc_problem* pr, long long t0, long long nsteps, double* f) {
+  lattice L;
+  size_t bytes;
+  double *a, *b;
+  long long i;
+  if (check_problem(pr, &L) || nsteps < 0) return -1;
+  bytes = sizeof(double) * (size_t)L.q * pr->nx * pr->ny * pr->nz;
+  b = (double*)malloc(bytes);
+  if (!b) return -2;
+  a = f;
+  for (i = 0; i < nsteps; ++i) {
+    double* tmp;
+    step_impl(pr, &L, t0 + i, a, b);
+    tmp = a;
+    a = b;
+    b = tmp;
+  }
+  if (a != f) {
+    memcpy(f, a, bytes);
+    free(a);
+  } else {
+    free(b);
+  }
+  return 0;
+}
+
+/* p (N) and u (3 x N) at time level t. */
+int orc_macros(const orc_problem* pr, long long t, const double* f, double* p, double* u) {
+  lattice L;
+  size_t N, n;
+  double F[3];
+  if (check_problem(pr, &L)) return -1;
+  N = (size_t)pr->nx * pr->ny * pr->nz;
+  force_at(pr, t, F);
+  for (n = 0; n < N; ++n) {
+    double fn[QMAX], un[3];
+    int a;
+    for (a = 0; a < L.q; ++a) fn[a] = f[(size_t)a * N + n];
+    macro_node(&L, fn, F, &p[n], un);
+    u[n] = un[0];
+    u[N + n] = un[1];
+    u[2 * N + n] = un[2];
+  }
+  return 0;
+}
+
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
