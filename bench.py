@@ -1,0 +1,187 @@
+"""Benchmark of the D3Q18 MRT lattice Boltzmann step on one MI355X.
+
+Workload (one "step" = one time step of the whole path: collision, streaming
+with bounce-back and the moving lid, plus the FP64 monitor every 1000
+steps): a 128^3 lid-driven cubic cavity, D3Q18, FP32 populations in SoA
+layout updated in place (AA pattern), lid speed 0.1, Re = 1000
+(nu = 0.0128).  Inputs are synthetic (the cavity starts at rest) and
+resident in HBM before timing starts.
+
+Prints one JSON line.  value = MLUPS (million lattice-node updates per
+second); the roofline block reads the step kernels against the 8 TB/s HBM
+peak using the algorithmic traffic of 2 q b = 144 bytes per node and step.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS & % HBM roofline (D3Q18 FP32); batched serving p50/p99 latency vs plain"
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_step_d3q18_f32_aa_cavity128.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1503_03337_amd", "csrc", f)
+                  for f in ("kernels.hip", "lattice.hpp", "kernels.hpp")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None if there is none or the kernels changed since."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    txt = open(PMC_SUMMARY).read()
+    m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def cavity_lattice(lbm, params, n, monitor_every=1000):
+    cfg = params.cavity(18, n, 1000.0, lid=0.1)
+    return lbm.Lattice(18, n, n, n, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"],
+                       storage="f32", pattern="aa", monitor_every=monitor_every)
+
+
+def time_steps(torch, lat, steps):
+    """Wall time and HIP-event time of `steps` steps on the lattice's stream."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1e3
+
+
+def copy_bandwidth(torch, lbm, nbytes=1 << 30, reps=20):
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    lbm.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, 2, stream.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lbm.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, reps, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    return 2.0 * nbytes / sec / 1e9
+
+
+def cpu_baseline(target_seconds=15.0):
+    """The FP64 oracle on the host cores: 128^3 D3Q18 cavity from rest."""
+    import numpy as np
+    from oracle import runner as R
+    from paper_1503_03337_amd import params
+    n = 128
+    cfg = params.cavity(18, n, 1000.0, lid=0.1)
+    pr = R.problem(18, n, n, n, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"])
+    f = R.init_eq(pr)
+    t0 = time.perf_counter()
+    f = R.run(pr, f, 0, 1)
+    one = time.perf_counter() - t0
+    k = max(1, int(target_seconds / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    f = R.run(pr, f, 1, k)
+    sec = time.perf_counter() - t0
+    assert np.isfinite(f).all()
+    return {"value": round(n ** 3 * k / sec / 1e6, 3), "unit": "MLUPS", "cores": R.threads(),
+            "kind": "oracle",
+            "sample": "D3Q18 128^3 lid-driven cavity, FP64, %d step(s) from rest (%.1f s), "
+                      "OpenMP over z planes" % (k, sec)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--size", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1503_03337_amd import lbm, params
+    torch.cuda.set_device(0)
+    n = args.size
+    N = n ** 3
+    lat = cavity_lattice(lbm, params, n)
+    lat.step(args.warmup)
+    wall, ev = time_steps(torch, lat, args.steps)
+    mlups = N * args.steps / wall / 1e6
+    r = lat.residual() if lat.time >= 2000 else None
+    lat.close()
+
+    bytes_per_node = 2 * 18 * 4
+    achieved = bytes_per_node * N / (ev / args.steps) / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+
+    # the same kernels on a lattice larger than the 256 MB Infinity Cache
+    big = cavity_lattice(lbm, params, 256, monitor_every=0)
+    big.step(20)
+    bsteps = 200
+    bwall, bev = time_steps(torch, big, bsteps)
+    big.close()
+    copy_gbs = copy_bandwidth(torch, lbm)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D3Q18 MRT lid-driven cavity %d^3, Re=1000 (nu=%.4g), lid 0.1, "
+                               "FP32 SoA populations, AA in-place streaming, FP64 monitor every "
+                               "1000 steps" % (n, 0.1 * n / 1000.0),
+                   "nodes": N, "bytes_per_node_step": bytes_per_node},
+        "roofline": roofline,
+        "hbm_roofline_fraction": round(mlups * 1e6 * bytes_per_node / (HBM_PEAK_GBS * 1e9), 4),
+        "residual_at_end": r,
+        "cavity256": {"MLUPS": round(256 ** 3 * bsteps / bwall / 1e6, 1),
+                      "achieved_GBs": round(bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9, 1)},
+        "copy_probe_GBs": round(copy_gbs, 1),
+    }
+    if not args.no_serving:
+        try:
+            from paper_1503_03337_amd import serve
+            out["serving"] = serve.bench_summary(torch)
+        except ImportError:
+            out["serving"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the incompressible
+ * 14- and 18-velocity multiple-relaxation-time lattice Boltzmann models of
+ * Zhang, Shi & Wang (arXiv 1503.03337).
+ *
+ * What one time step computes (per fluid node x, time level t -> t+1):
+ *   - P = sum_a f_a, j = sum_a c_a f_a, u = j + F(t)/2 and
+ *     p = c_s^2/(1-w0) [P - w0 |u|^2 / (2 c_s^2)]          (Eq. (hgl))
+ *   - m = T f with the integer T of Eq. (T14) / Appendix B (Sec. 3)
+ *   - D_k = s_k (m_k - m_k^eq(p,u)) - (1 - s_k/2) m_k^F     (Eq. (mrteqvT);
+ *     m^eq from Eq. (meq) / Appendix B, m^F = (d m^eq/d u) . F, the body
+ *     force written in moment space; F = 0 is the paper's scheme)
+ *   - f*_a = f_a - sum_k T_ka D_k / N_k, N_k = sum_a T_ka^2 (rows of T are
+ *     orthogonal, Sec. 3)
+ *   - streaming f_a(x + c_a, t+1) = f*_a(x) (Eq. (mrteq)); periodic faces
+ *     wrap; across a wall face the population returns as
+ *     f_abar(x, t+1) = f*_a(x) - 6 w_a (c_a . u_w) (half-way bounce-back
+ *     with the moving-wall term of the linear part of Eq. (edf)).  A link
+ *     leaving through several wall faces takes the wall velocity of its z
+ *     face, else its y face, else its x face.
+ *
+ * Lattice units (c = dx = dt = 1, c_s^2 = 1/3).  Velocities in the paper's
+ * order: q = 14 (Sec. 3): +-x, +-y, +-z, then the 8 corners
+ * (1,1,1),(-1,1,1),(1,-1,1),(-1,-1,1),(1,1,-1),(-1,1,-1),(1,-1,-1),
+ * (-1,-1,-1); q = 18 (Appendix B): +-x, +-y, +-z, then (+-1,+-1,0),
+ * (+-1,0,+-1), (0,+-1,+-1), x sign varying fastest.  Weights: 1/9, 1/72
+ * (rest weight 2/9) for q = 14 -- the D3Q15 values, since the printed
+ * Eq. (omega) values do not reproduce Eq. (meq) -- and 1/18, 1/36 (rest
+ * weight 1/3) for q = 18.  Relaxation vectors s_vec hold q rates in the
+ * moment order of Eq. (moment) / Eq. (d3q18moment).
+ *
+ * Node (i,j,k) has linear index n = i + nx*(j + ny*k); host population
+ * arrays are [q][N] FP64 in that order, macroscopic arrays p[N], u[3][N].
+ * Walls are half-way: fluid nodes 0..n-1, wall planes at -1/2 and n-1/2.
+ *
+ * Conventions: every function returns LBM_OK (0) or a negative lbm_status;
+ * nothing throws across the ABI.  The library owns all device state of a
+ * context unless spec.dev_buf is given, in which case the caller owns that
+ * buffer (and must keep it alive until lbm_destroy) and the library never
+ * frees it.  Host arrays are always caller-owned and only read/written
+ * during the call.  Work is queued on spec.stream (a hipStream_t; NULL =
+ * the null stream); calls that return host data synchronise that stream.
+ * A context is not thread-safe; use one context per host thread.
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+typedef enum { LBM_D3Q14 = 14, LBM_D3Q18 = 18 } lbm_model;
+
+/* Population storage.  Arithmetic is FP64 for LBM_F64 and FP32 otherwise.
+ * LBM_F16DEV stores h_a = fp16((f_a - 3 w_a p0) 2^s): the deviation from the
+ * rest-state equilibrium f_a = 3 w_a p0 (Eq. (edf) at u = 0), scaled by a
+ * power of two (exact) so that it stays in FP16's normal range. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2 } lbm_storage;
+
+/* Streaming pattern: LBM_AB keeps two population copies (read one, write
+ * the other); LBM_AA keeps one copy updated in place, alternating a local
+ * step (read and write a node's own slots) and a neighbour step. */
+typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
+
+typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_face_kind;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument: q, dims < 1, N >= 2^31, s_k outside [0,2),
+                          unpaired periodic faces, |u_w| >= 0.3, bad storage ... */
+  LBM_ENOMEM = -2,     /* footprint above dev_buf_bytes or hipMalloc failure */
+  LBM_EDEVICE = -3,    /* a HIP call failed (message in lbm_last_error) */
+  LBM_ENONFINITE = -4, /* a monitor found a non-finite mass or velocity */
+  LBM_ESTATE = -5      /* call not valid in this state (e.g. no monitor data) */
+} lbm_status;
+
+/* Faces in the order -x, +x, -y, +y, -z, +z. */
+typedef struct {
+  int face[6];          /* lbm_face_kind; periodic faces must come in pairs   */
+  double wall_u[6][3];  /* velocity of each wall face (0 = no-slip)          */
+  double F0[3];         /* body force F(t) = F0 + FA cos(2 pi t / FT)         */
+  double FA[3];
+  double FT;            /* FT <= 0: constant force F0                        */
+  double p0;            /* reference pressure: initial state and FP16 base   */
+  double u0[3];         /* initial velocity: f = f_eq(p0, u0 - F(0)/2)       */
+  int storage;          /* lbm_storage                                       */
+  int pattern;          /* lbm_pattern                                       */
+  int f16_scale_log2;   /* s of LBM_F16DEV, 0..24                           */
+  int monitor_every;    /* K > 0: run the mass/residual monitor every K steps */
+  void* stream;         /* hipStream_t to queue work on (NULL: null stream)  */
+  void* dev_buf;        /* optional caller-owned device buffer ...           */
+  size_t dev_buf_bytes; /* ... and its size (>= lbm_footprint_bytes)         */
+} lbm_spec;
+
+/* Defaults: all six faces walls at rest, no force, p0 = 0, u0 = 0, FP32,
+ * AA pattern, f16_scale_log2 = 12, no monitor, null stream, own memory. */
+void lbm_spec_default(lbm_spec* spec);
+
+/* Device bytes a context of this shape needs (populations, monitor
+ * snapshot and reduction scratch); 0 on invalid input.  For admission
+ * control: no device call is made. */
+size_t lbm_footprint_bytes(int model, int nx, int ny, int nz, const lbm_spec* spec);
+
+/* Create a context and initialise f = f_eq(p0, u0 - F(0)/2) at t = 0
+ * (Eq. (edf)).  s_vec: q relaxation rates in moment order, each in [0,2). */
+int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz,
+               const double* s_vec, const lbm_spec* spec);
+
+/* Advance n >= 0 time steps (one kernel launch per step, queued on the
+ * context stream; returns without waiting). */
+int lbm_step(lbm_ctx* ctx, long long n);
+
+/* Pressure p[N] and velocity u[3][N] (host, FP64) at the current time level
+ * t, with u = sum c f + F(t)/2 (Eq. (hgl)).  Either pointer may be NULL.
+ * Synchronises the stream. */
+int lbm_macros(lbm_ctx* ctx, double* p, double* u);
+
+/* Same, into caller-owned device FP64 arrays; queued, does not wait. */
+int lbm_macros_device(lbm_ctx* ctx, double* p_dev, double* u_dev);
+
+/* Velocity residual of the last monitor run:
+ *   R = sum_n sum_k |u_k(n,t) - u_k(n,t-L)| / (L sum_n sum_k |u_k(n,t)|)
+ * with L the steps since the previous snapshot (the steady-state criteria
+ * Eqs. (sc), (cr), (cavity_creterion) for lag L, per step).  +inf when
+ * sum|u| = 0 or before a second snapshot.  LBM_ENONFINITE if the monitor saw
+ * a non-finite value.  Synchronises the stream. */
+int lbm_residual(lbm_ctx* ctx, double* r);
+
+/* Mass M = sum_n P(n) = sum_n sum_a f_a(n) (FP64) from the last monitor run;
+ * runs the monitor first if it has never run. */
+int lbm_mass(lbm_ctx* ctx, double* m);
+
+/* Run the monitor now (snapshot u, update residual and mass); queued. */
+int lbm_monitor(lbm_ctx* ctx);
+
+/* Populations at the current time level as host FP64 [q][N], in the
+ * physical (streamed, decoded) layout whatever the pattern and parity. */
+int lbm_get_f(lbm_ctx* ctx, double* f);
+
+/* Overwrite the populations from host FP64 [q][N] (encoded to the storage
+ * type); the time level is unchanged.  Synchronises the stream. */
+int lbm_set_f(lbm_ctx* ctx, const double* f);
+
+/* Set f = f_eq(p, u - F(t)/2) from host FP64 p[N], u[3][N] (NULL: p0 / u0),
+ * so that the velocity recovered at the current time t is u. */
+int lbm_init_fields(lbm_ctx* ctx, const double* p, const double* u);
+
+long long lbm_time(const lbm_ctx* ctx);
+int lbm_set_time(lbm_ctx* ctx, long long t);   /* for checkpoint restore */
+
+/* Shape and device layout of a context (for drivers and measurement). */
+typedef struct {
+  int q, nx, ny, nz, storage, pattern;
+  long long t;
+  size_t nodes;             /* nx*ny*nz                                     */
+  size_t population_bytes;  /* bytes of one population copy (q*N*elem)      */
+  size_t footprint_bytes;   /* everything the context holds on the device   */
+  int bytes_per_value;      /* 8, 4 or 2                                    */
+} lbm_info_t;
+int lbm_info(const lbm_ctx* ctx, lbm_info_t* info);
+
+int lbm_sync(lbm_ctx* ctx);                  /* wait for the context stream */
+/* Message of the last failure on ctx; with ctx == NULL, of the last failed
+ * lbm_create on the calling thread.  Never NULL. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+const char* lbm_status_string(int status);
+int lbm_destroy(lbm_ctx* ctx);
+
+/* ---- batched execution ------------------------------------------------
+ * A batch advances many independent contexts (any mix of q = 14 / 18,
+ * storage FP32 / FP16DEV, pattern AA, shapes, boundaries, forces and
+ * rates) with one kernel launch per time step covering all of them; each
+ * member keeps its own time level, parity and populations, and its result
+ * is bit-identical to running it alone in a batch.  Members must share the
+ * batch's stream.  Members can be added and removed between calls
+ * (continuous batching).  Each member has a step budget: lbm_batch_step
+ * advances it by min(n, remaining budget). */
+int lbm_batch_create(lbm_batch** out, void* stream);
+int lbm_batch_add(lbm_batch* b, lbm_ctx* ctx, long long step_budget);
+int lbm_batch_remove(lbm_batch* b, lbm_ctx* ctx);
+/* Tile of a member: tx*ty <= 256 nodes of one x-y plane per workgroup
+ * (0,0 = automatic). */
+int lbm_batch_set_tile(lbm_batch* b, lbm_ctx* ctx, int tx, int ty);
+int lbm_batch_step(lbm_batch* b, long long n);
+/* Run every member's monitor (one launch); then lbm_residual / lbm_mass of
+ * each member read its values. */
+int lbm_batch_monitor(lbm_batch* b);
+/* Remaining step budget of a member (0 when done); -1 if not a member. */
+long long lbm_batch_remaining(const lbm_batch* b, const lbm_ctx* ctx);
+int lbm_batch_size(const lbm_batch* b);
+const char* lbm_batch_last_error(const lbm_batch* b);
+int lbm_batch_destroy(lbm_batch* b);
+
+/* ---- measurement helper -----------------------------------------------
+ * Copy `bytes` (multiple of 16) from src to dst on the device with a plain
+ * streaming kernel, `reps` times back to back; the achievable-bandwidth
+ * reference against which the step kernels are read.  Queued on stream. */
+int lbm_copy_probe(void* dst, const void* src, size_t bytes, int reps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H_ */

@@ -1,0 +1,854 @@
+// kernels.hip -- device code of the D3Q14 / D3Q18 incompressible MRT
+// lattice Boltzmann library for gfx950 (arXiv 1503.03337).
+//
+// Data layout: structure of arrays, population a of node n at
+// f[a*stride + n], n = x + nx*(y + ny*z); one thread per node, a workgroup
+// covers a tx x ty tile of one x-y plane (tx spans whole rows where it can,
+// so a wavefront reads and writes 64 consecutive x).  Every population is
+// read once and written once per step: the kernels are HBM-bound
+// (2 q b bytes per node, b = bytes per stored value).
+//
+// One time step (Eq. (mrteq)): collide every node (lattice.hpp), then move
+// each post-collision population to x + c_a; across a periodic face the
+// destination wraps, across a wall face it returns to x as the opposite
+// population minus 6 w_a (c_a . u_w) (half-way bounce-back, moving wall).
+// Three memory patterns:
+//   AB       read A[a][n]; push f*_a to B[a][n + c_a] (or B[abar][n])
+//   AA even  read A[a][n]; write f*_a to A[abar][n] (purely local; minus
+//            the wall term when x + c_a is a wall)
+//   AA odd   read f_a = A[abar][n - c_a] (or A[a][n] when n - c_a is a
+//            wall); push like AB but in place
+// AA even + AA odd = two time steps on one copy; each node reads and
+// writes exactly the same set of slots within a step, so the in-place
+// update has no race.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace lbm {
+
+// Launch helpers read hipGetLastError() after a launch; drop any error an
+// earlier, unrelated runtime call left behind so only this launch counts.
+static inline void clear_stale_error() { (void)hipGetLastError(); }
+
+// ---- storage codecs --------------------------------------------------------
+template <int ST> struct Codec;
+template <> struct Codec<ST_F64> {
+  using S = double;
+  using C = double;
+  static __device__ __forceinline__ C dec(S v, C, C) { return v; }
+  static __device__ __forceinline__ S enc(C v, C, C) { return v; }
+};
+template <> struct Codec<ST_F32> {
+  using S = float;
+  using C = float;
+  static __device__ __forceinline__ C dec(S v, C, C) { return v; }
+  static __device__ __forceinline__ S enc(C v, C, C) { return v; }
+};
+// FP16 deviation: stored h = fp16((f - base) 2^s); 2^s and 2^-s are exact.
+template <> struct Codec<ST_F16> {
+  using S = _Float16;
+  using C = float;
+  static __device__ __forceinline__ C dec(S v, C base, C inv_scale) {
+    return base + static_cast<float>(v) * inv_scale;
+  }
+  static __device__ __forceinline__ S enc(C v, C base, C scale) {
+    return static_cast<_Float16>((v - base) * scale);
+  }
+};
+
+// ---- neighbour offsets -----------------------------------------------------
+// For each axis and direction (-1, +1): the linear-index delta of the
+// neighbour (wrapped on periodic axes) and whether a wall is crossed.
+struct Nbr {
+  int ox[2], oy[2], oz[2];
+  bool wx[2], wy[2], wz[2];
+};
+
+__device__ __forceinline__ void axis_nbr(int c, int n, int per, int stride, int (&o)[2],
+                                         bool (&w)[2]) {
+  const bool lo = (c == 0), hi = (c == n - 1);
+  o[0] = lo ? (per ? (n - 1) * stride : 0) : -stride;
+  o[1] = hi ? (per ? -(n - 1) * stride : 0) : stride;
+  w[0] = lo && !per;
+  w[1] = hi && !per;
+}
+
+// GEN = false: the caller guarantees 0 < y < ny-1 and 0 < z < nz-1, so only
+// x needs boundary handling (per lane); GEN = true handles every axis.
+template <bool GEN, typename C>
+__device__ __forceinline__ Nbr make_nbr(const LatticeArgs<C>& A, int x, int y, int z) {
+  Nbr b;
+  axis_nbr(x, A.nx, A.per_x, 1, b.ox, b.wx);
+  if (GEN) {
+    axis_nbr(y, A.ny, A.per_y, A.nx, b.oy, b.wy);
+    axis_nbr(z, A.nz, A.per_z, A.nx * A.ny, b.oz, b.wz);
+  } else {
+    b.oy[0] = -A.nx;
+    b.oy[1] = A.nx;
+    b.oz[0] = -A.nx * A.ny;
+    b.oz[1] = A.nx * A.ny;
+    b.wy[0] = b.wy[1] = b.wz[0] = b.wz[1] = false;
+  }
+  return b;
+}
+
+// Link from this node along direction (cx,cy,cz): offset, wall flag and
+// the wall term of population `a` leaving through the crossed face (z face
+// first, then y, then x).
+template <int Q, typename C>
+__device__ __forceinline__ void link(const Nbr& b, const LatticeArgs<C>& A, int a, int cx, int cy,
+                                     int cz, int& off, bool& wall, C& term) {
+  off = 0;
+  wall = false;
+  term = C(0);
+  if (cx) {
+    const int k = cx > 0;
+    off += b.ox[k];
+    if (b.wx[k]) {
+      wall = true;
+      term = A.bb[a][0];
+    }
+  }
+  if (cy) {
+    const int k = cy > 0;
+    off += b.oy[k];
+    if (b.wy[k]) {
+      wall = true;
+      term = A.bb[a][1];
+    }
+  }
+  if (cz) {
+    const int k = cz > 0;
+    off += b.oz[k];
+    if (b.wz[k]) {
+      wall = true;
+      term = A.bb[a][2];
+    }
+  }
+}
+
+// ---- reading the populations of node n ------------------------------------
+// PHASE 0: natural layout (AB, AA even).  PHASE 1: AA swapped layout after
+// an even step: f_a(x) = A[abar][x - c_a], or, when x - c_a is a wall,
+// A[a][x], where the even step already stored the bounced-back value
+// f*_abar(x) - 6 w_abar (c_abar . u_w).
+template <int Q, int ST, int PHASE, bool GEN>
+__device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::C>& A,
+                                          const typename Codec<ST>::S* src, unsigned n, int x,
+                                          int y, int z, typename Codec<ST>::C (&f)[Q]) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  using L = Lattice<Q>;
+  const long long st = A.stride;
+  if (PHASE == 0) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) f[a] = CD::dec(src[a * st + n], A.base[a], A.inv_scale);
+  } else {
+    const Nbr b = make_nbr<GEN>(A, x, y, z);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int o = L::opp[a];
+      int off;
+      bool wall;
+      C term;
+      link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term);
+      const long long idx = wall ? (a * st + n) : (o * st + (long long)(n + off));
+      f[a] = CD::dec(src[idx], A.base[a], A.inv_scale);
+    }
+  }
+}
+
+// ---- writing post-collision populations -----------------------------------
+// MODE_AA_EVEN: f*_a into slot abar of the same node, minus the wall term
+// when x + c_a is a wall (so the value stored is the bounced-back
+// population, rounded once, as in the push patterns).  Otherwise push to
+// x + c_a (or bounce back into slot abar of this node across a wall).
+template <int Q, int ST, int MODE, bool GEN>
+__device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>::C>& A,
+                                           typename Codec<ST>::S* dst, unsigned n, int x, int y,
+                                           int z, const typename Codec<ST>::C (&f)[Q]) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  using L = Lattice<Q>;
+  const long long st = A.stride;
+  if (MODE == MODE_AA_EVEN) {
+    const Nbr b = make_nbr<GEN>(A, x, y, z);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int o = L::opp[a];
+      int off;
+      bool wall;
+      C term;
+      link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term);
+      dst[o * st + n] = CD::enc(wall ? f[a] - term : f[a], A.base[o], A.scale);
+    }
+  } else {
+    const Nbr b = make_nbr<GEN>(A, x, y, z);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int o = L::opp[a];
+      int off;
+      bool wall;
+      C term;
+      link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term);
+      if (wall)
+        dst[o * st + n] = CD::enc(f[a] - term, A.base[o], A.scale);
+      else
+        dst[a * st + (long long)(n + off)] = CD::enc(f[a], A.base[a], A.scale);
+    }
+  }
+}
+
+// ---- one node, one step ------------------------------------------------------
+template <int Q, int ST, int MODE, bool FORCED, bool GEN>
+__device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::C>& A, int x, int y,
+                                          int z) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  using S = typename CD::S;
+  const unsigned n = (unsigned)x + (unsigned)A.nx * ((unsigned)y + (unsigned)A.ny * (unsigned)z);
+  C f[Q];
+  if (MODE == MODE_AB) {
+    read_node<Q, ST, 0, GEN>(A, static_cast<const S* __restrict__>(A.f), n, x, y, z, f);
+  } else if (MODE == MODE_AA_EVEN) {
+    read_node<Q, ST, 0, GEN>(A, static_cast<const S*>(A.f), n, x, y, z, f);
+  } else {
+    read_node<Q, ST, 1, GEN>(A, static_cast<const S*>(A.f), n, x, y, z, f);
+  }
+  Relax<C> r;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    r.sN[k] = A.sN[k];
+    r.hN[k] = A.hN[k];
+  }
+  C F[3] = {A.F[0], A.F[1], A.F[2]};
+  collide<Q, C, FORCED>(f, r, F);
+  write_node<Q, ST, MODE, GEN>(A, static_cast<S*>(MODE == MODE_AB ? A.g : A.f), n, x, y, z, f);
+}
+
+// Dispatch on whether this node's wavefront may touch a y or z boundary
+// (uniform for a wavefront inside one x-row).
+template <int Q, int ST, int MODE, bool FORCED>
+__device__ __forceinline__ void node_step_any(const LatticeArgs<typename Codec<ST>::C>& A, int x,
+                                              int y, int z) {
+  const bool inner = (y > 0) & (y < A.ny - 1) & (z > 0) & (z < A.nz - 1);
+  if (inner)
+    node_step<Q, ST, MODE, FORCED, false>(A, x, y, z);
+  else
+    node_step<Q, ST, MODE, FORCED, true>(A, x, y, z);
+}
+
+template <int Q, int ST, int MODE, bool FORCED>
+__global__ __launch_bounds__(256) void k_step(LatticeArgs<typename Codec<ST>::C> A) {
+  const int b = blockIdx.x;
+  const int bx = b % A.tiles_x;
+  const int r = b / A.tiles_x;
+  const int by = r % A.tiles_y;
+  const int z = r / A.tiles_y;
+  const int x = bx * A.tx + (int)threadIdx.x;
+  const int y = by * A.ty + (int)threadIdx.y;
+  if (x >= A.nx || y >= A.ny) return;
+  node_step_any<Q, ST, MODE, FORCED>(A, x, y, z);
+}
+
+template <int Q, int ST, int MODE, bool FORCED>
+static hipError_t step_launch(const void* args, hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const long long blocks = (long long)A.tiles_x * A.tiles_y * A.nz;
+  dim3 block(A.tx, A.ty, 1);
+  hipLaunchKernelGGL((k_step<Q, ST, MODE, FORCED>), dim3((unsigned)blocks), block, 0, s, A);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t step_q_st(int mode, bool forced, const void* args, hipStream_t s) {
+  clear_stale_error();
+  switch (mode) {
+    case MODE_AB:
+      return forced ? step_launch<Q, ST, MODE_AB, true>(args, s)
+                    : step_launch<Q, ST, MODE_AB, false>(args, s);
+    case MODE_AA_EVEN:
+      return forced ? step_launch<Q, ST, MODE_AA_EVEN, true>(args, s)
+                    : step_launch<Q, ST, MODE_AA_EVEN, false>(args, s);
+    case MODE_AA_ODD:
+      return forced ? step_launch<Q, ST, MODE_AA_ODD, true>(args, s)
+                    : step_launch<Q, ST, MODE_AA_ODD, false>(args, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int q, int storage, int mode, bool forced, const void* args, size_t,
+                       hipStream_t s) {
+  clear_stale_error();
+  if (q == 14) {
+    if (storage == ST_F64) return step_q_st<14, ST_F64>(mode, forced, args, s);
+    if (storage == ST_F32) return step_q_st<14, ST_F32>(mode, forced, args, s);
+    if (storage == ST_F16) return step_q_st<14, ST_F16>(mode, forced, args, s);
+  } else if (q == 18) {
+    if (storage == ST_F64) return step_q_st<18, ST_F64>(mode, forced, args, s);
+    if (storage == ST_F32) return step_q_st<18, ST_F32>(mode, forced, args, s);
+    if (storage == ST_F16) return step_q_st<18, ST_F16>(mode, forced, args, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---- grid-stride helpers for the auxiliary kernels -------------------------
+__device__ __forceinline__ void node_xyz(long long n, int nx, int ny, int& x, int& y, int& z) {
+  x = (int)(n % nx);
+  const long long r = n / nx;
+  y = (int)(r % ny);
+  z = (int)(r / ny);
+}
+
+// ---- population get / set / init -------------------------------------------
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_get_pop(LatticeArgs<typename Codec<ST>::C> A, int a,
+                                                 double* __restrict__ out) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  const long long N = (long long)A.nx * A.ny * A.nz;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
+       n += (long long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    node_xyz(n, A.nx, A.ny, x, y, z);
+    C f[Q];
+    read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), (unsigned)n, x, y, z,
+                                  f);
+    // select population a without dynamic register indexing
+    C v = f[0];
+#pragma unroll
+    for (int k = 1; k < Q; ++k)
+      if (k == a) v = f[k];
+    out[n] = (double)v;
+  }
+}
+
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_set_pop(LatticeArgs<typename Codec<ST>::C> A, int a,
+                                                 const double* __restrict__ in) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  const long long N = (long long)A.nx * A.ny * A.nz;
+  typename CD::S* dst = static_cast<typename CD::S*>(A.f) + a * A.stride;
+  C base = A.base[0];
+#pragma unroll
+  for (int k = 1; k < Q; ++k)
+    if (k == a) base = A.base[k];
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
+       n += (long long)gridDim.x * blockDim.x)
+    dst[n] = CD::enc((C)in[n], base, A.scale);
+}
+
+// Eq. (edf) with Eq. (lamda_alpha): f_a = 3 w_a p + w_a (3 c.u + 9/2 (c.u)^2
+// - 3/2 |u|^2), evaluated in FP64 with j = u - F/2.
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_init_eq(LatticeArgs<typename Codec<ST>::C> A,
+                                                 const double* __restrict__ p,
+                                                 const double* __restrict__ u, double p0, double u0x,
+                                                 double u0y, double u0z, double Fx, double Fy,
+                                                 double Fz) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  using L = Lattice<Q>;
+  const long long N = (long long)A.nx * A.ny * A.nz;
+  typename CD::S* dst = static_cast<typename CD::S*>(A.f);
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
+       n += (long long)gridDim.x * blockDim.x) {
+    const double pn = p ? p[n] : p0;
+    const double jx = (u ? u[n] : u0x) - 0.5 * Fx;
+    const double jy = (u ? u[N + n] : u0y) - 0.5 * Fy;
+    const double jz = (u ? u[2 * N + n] : u0z) - 0.5 * Fz;
+    const double jsq = jx * jx + jy * jy + jz * jz;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const double w = weight<Q>(a);
+      const double cu = L::cx[a] * jx + L::cy[a] * jy + L::cz[a] * jz;
+      const double fe = 3.0 * w * pn + w * (3.0 * cu + 4.5 * cu * cu - 1.5 * jsq);
+      dst[a * A.stride + n] = CD::enc((C)fe, A.base[a], A.scale);
+    }
+  }
+}
+
+static int aux_blocks(long long N) {
+  long long b = (N + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+#define DISPATCH_QST(q, st, CALL)                      \
+  do {                                                 \
+    if ((q) == 14) {                                   \
+      if ((st) == ST_F64) { constexpr int Q_ = 14; constexpr int ST_ = ST_F64; CALL; } \
+      if ((st) == ST_F32) { constexpr int Q_ = 14; constexpr int ST_ = ST_F32; CALL; } \
+      if ((st) == ST_F16) { constexpr int Q_ = 14; constexpr int ST_ = ST_F16; CALL; } \
+    } else if ((q) == 18) {                            \
+      if ((st) == ST_F64) { constexpr int Q_ = 18; constexpr int ST_ = ST_F64; CALL; } \
+      if ((st) == ST_F32) { constexpr int Q_ = 18; constexpr int ST_ = ST_F32; CALL; } \
+      if ((st) == ST_F16) { constexpr int Q_ = 18; constexpr int ST_ = ST_F16; CALL; } \
+    }                                                  \
+    return hipErrorInvalidValue;                       \
+  } while (0)
+
+template <int Q, int ST>
+static hipError_t get_pop_impl(int phase, const void* args, int a, double* out, hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const int nb = aux_blocks((long long)A.nx * A.ny * A.nz);
+  if (phase == 0)
+    hipLaunchKernelGGL((k_get_pop<Q, ST, 0>), dim3(nb), dim3(256), 0, s, A, a, out);
+  else
+    hipLaunchKernelGGL((k_get_pop<Q, ST, 1>), dim3(nb), dim3(256), 0, s, A, a, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_pop(int q, int storage, int phase, int a, const void* args, double* out,
+                          hipStream_t s) {
+  clear_stale_error();
+  DISPATCH_QST(q, storage, return (get_pop_impl<Q_, ST_>(phase, args, a, out, s)));
+}
+
+template <int Q, int ST>
+static hipError_t set_pop_impl(const void* args, int a, const double* in, hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const int nb = aux_blocks((long long)A.nx * A.ny * A.nz);
+  hipLaunchKernelGGL((k_set_pop<Q, ST>), dim3(nb), dim3(256), 0, s, A, a, in);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_pop(int q, int storage, int a, const void* args, const double* in,
+                          hipStream_t s) {
+  clear_stale_error();
+  DISPATCH_QST(q, storage, return (set_pop_impl<Q_, ST_>(args, a, in, s)));
+}
+
+template <int Q, int ST>
+static hipError_t init_impl(const void* args, const double* p, const double* u, double p0,
+                            const double* u0, hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const int nb = aux_blocks((long long)A.nx * A.ny * A.nz);
+  hipLaunchKernelGGL((k_init_eq<Q, ST>), dim3(nb), dim3(256), 0, s, A, p, u, p0, u0[0], u0[1],
+                     u0[2], (double)A.F[0], (double)A.F[1], (double)A.F[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_eq(int q, int storage, const void* args, const double* p, const double* u,
+                          double p0, const double* u0, hipStream_t s) {
+  clear_stale_error();
+  DISPATCH_QST(q, storage, return (init_impl<Q_, ST_>(args, p, u, p0, u0, s)));
+}
+
+// ---- macroscopic fields and monitors ----------------------------------------
+// P = sum f, j = sum c f (FP64 sums of the decoded values), u = j + F/2,
+// p by Eq. (hgl).
+template <int Q, typename C>
+__device__ __forceinline__ void macro_fp64(const C (&f)[Q], const C (&F)[3], double& P, double& ux,
+                                           double& uy, double& uz) {
+  using L = Lattice<Q>;
+  P = 0.0;
+  double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const double v = (double)f[a];
+    P += v;
+    if (L::cx[a]) jx += L::cx[a] > 0 ? v : -v;
+    if (L::cy[a]) jy += L::cy[a] > 0 ? v : -v;
+    if (L::cz[a]) jz += L::cz[a] > 0 ? v : -v;
+  }
+  ux = jx + 0.5 * (double)F[0];
+  uy = jy + 0.5 * (double)F[1];
+  uz = jz + 0.5 * (double)F[2];
+}
+
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_macros(LatticeArgs<typename Codec<ST>::C> A,
+                                                double* __restrict__ p, double* __restrict__ u) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  using L = Lattice<Q>;
+  const long long N = (long long)A.nx * A.ny * A.nz;
+  const C F[3] = {A.F[0], A.F[1], A.F[2]};
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
+       n += (long long)gridDim.x * blockDim.x) {
+    int x, y, z;
+    node_xyz(n, A.nx, A.ny, x, y, z);
+    C f[Q];
+    read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), (unsigned)n, x, y, z,
+                                  f);
+    double P, ux, uy, uz;
+    macro_fp64<Q, C>(f, F, P, ux, uy, uz);
+    const double usq = ux * ux + uy * uy + uz * uz;
+    if (p) p[n] = (P - 1.5 * L::w0 * usq) / (3.0 * (1.0 - L::w0));
+    if (u) {
+      u[n] = ux;
+      u[N + n] = uy;
+      u[2 * N + n] = uz;
+    }
+  }
+}
+
+template <int Q, int ST>
+static hipError_t macros_impl(int phase, const void* args, double* p, double* u, hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const int nb = aux_blocks((long long)A.nx * A.ny * A.nz);
+  if (phase == 0)
+    hipLaunchKernelGGL((k_macros<Q, ST, 0>), dim3(nb), dim3(256), 0, s, A, p, u);
+  else
+    hipLaunchKernelGGL((k_macros<Q, ST, 1>), dim3(nb), dim3(256), 0, s, A, p, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_macros(int q, int storage, int phase, const void* args, double* p, double* u,
+                         hipStream_t s) {
+  clear_stale_error();
+  DISPATCH_QST(q, storage, return (macros_impl<Q_, ST_>(phase, args, p, u, s)));
+}
+
+// Deterministic block sum of three FP64 values: wavefront butterfly by
+// xor-shuffles, then the 4 wavefront results in fixed order.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    a += __shfl_xor(a, m, 64);
+    b += __shfl_xor(b, m, 64);
+    c += __shfl_xor(c, m, 64);
+  }
+  __shared__ double sh[3][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wv] = a;
+    sh[1][wv] = b;
+    sh[2][wv] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    b = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    c = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
+  }
+}
+
+static constexpr int MON_BLOCKS_MAX = 2048;
+int monitor_blocks(long long nodes) {
+  long long b = (nodes + 255) / 256;
+  if (b > MON_BLOCKS_MAX) b = MON_BLOCKS_MAX;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// Pass 1 over nodes [n_begin, n_end) of one lattice, grid-strided by the
+// blocks [0, nblk): sums |u - snap|, |u|, P; snap <- u.
+template <int Q, int ST, int PHASE>
+__device__ __forceinline__ void monitor_body(const LatticeArgs<typename Codec<ST>::C>& A,
+                                             typename Codec<ST>::C* __restrict__ snap, int blk,
+                                             int nblk, double& s_du, double& s_u, double& s_P) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  const long long N = (long long)A.nx * A.ny * A.nz;
+  const C F[3] = {A.F[0], A.F[1], A.F[2]};
+  s_du = s_u = s_P = 0.0;
+  for (long long n = blk * 256LL + threadIdx.x; n < N; n += (long long)nblk * 256) {
+    int x, y, z;
+    node_xyz(n, A.nx, A.ny, x, y, z);
+    C f[Q];
+    read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), (unsigned)n, x, y, z,
+                                  f);
+    double P, ux, uy, uz;
+    macro_fp64<Q, C>(f, F, P, ux, uy, uz);
+    const double o0 = (double)snap[n], o1 = (double)snap[N + n], o2 = (double)snap[2 * N + n];
+    s_du += fabs(ux - o0) + fabs(uy - o1) + fabs(uz - o2);
+    s_u += fabs(ux) + fabs(uy) + fabs(uz);
+    s_P += P;
+    snap[n] = (C)ux;
+    snap[N + n] = (C)uy;
+    snap[2 * N + n] = (C)uz;
+  }
+  block_sum3(s_du, s_u, s_P);
+}
+
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_monitor(LatticeArgs<typename Codec<ST>::C> A,
+                                                 typename Codec<ST>::C* __restrict__ snap,
+                                                 double* __restrict__ partial) {
+  double a, b, c;
+  monitor_body<Q, ST, PHASE>(A, snap, blockIdx.x, gridDim.x, a, b, c);
+  if (threadIdx.x == 0) {
+    partial[3 * blockIdx.x + 0] = a;
+    partial[3 * blockIdx.x + 1] = b;
+    partial[3 * blockIdx.x + 2] = c;
+  }
+}
+
+template <int Q, int ST>
+static hipError_t monitor_impl(int phase, const void* args, void* snap, double* partial, int* nbo,
+                               hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const int nb = monitor_blocks((long long)A.nx * A.ny * A.nz);
+  *nbo = nb;
+  if (phase == 0)
+    hipLaunchKernelGGL((k_monitor<Q, ST, 0>), dim3(nb), dim3(256), 0, s, A, (C*)snap, partial);
+  else
+    hipLaunchKernelGGL((k_monitor<Q, ST, 1>), dim3(nb), dim3(256), 0, s, A, (C*)snap, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_monitor(int q, int storage, int phase, const void* args, void* snap,
+                          double* partial, int* nbo, hipStream_t s) {
+  clear_stale_error();
+  DISPATCH_QST(q, storage, return (monitor_impl<Q_, ST_>(phase, args, snap, partial, nbo, s)));
+}
+
+// Pass 2: one workgroup, fixed-order sum of nb partial triples.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial,
+                                                         int nb, double* __restrict__ out) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a += partial[3 * i];
+    b += partial[3 * i + 1];
+    c += partial[3 * i + 2];
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+  }
+}
+
+hipError_t launch_reduce_partials(const double* partial, int nb, double* out, hipStream_t s) {
+  clear_stale_error();
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+// ---- measurement helper: plain streaming copy ---------------------------------
+__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
+                                              uint4* __restrict__ dst, long long n16) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n16; i += (long long)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  clear_stale_error();
+  const long long n16 = (long long)(bytes / 16);
+  long long nb = (n16 + 255) / 256;
+  if (nb > 256 * 64) nb = 256 * 64;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, (const uint4*)src, (uint4*)dst,
+                     n16);
+  return hipGetLastError();
+}
+
+// ---- batched execution --------------------------------------------------------
+// One launch per time step over the tiles of every member.  A workgroup
+// finds its member by binary search over the members' first tile indices
+// (uniform scalar loads), then runs the same node update as k_step for that
+// member's q, storage, parity and force.  Per-member arithmetic does not
+// depend on the other members, so a member's result is the same alone and
+// in any mix.
+template <int Q, int ST, bool FORCED>
+__device__ __forceinline__ void batch_node(const BatchMember& m, int phase, const float* ftab,
+                                           int substep, int x, int y, int z) {
+  if (ST == ST_F32) {
+    LatticeArgs<float> A = m.a;
+    if (FORCED) {
+      const float* Fr = ftab + m.ftab_off + 3LL * substep;
+      A.F[0] = Fr[0];
+      A.F[1] = Fr[1];
+      A.F[2] = Fr[2];
+    }
+    if (phase == 0)
+      node_step_any<Q, ST_F32, MODE_AA_EVEN, FORCED>(A, x, y, z);
+    else
+      node_step_any<Q, ST_F32, MODE_AA_ODD, FORCED>(A, x, y, z);
+  } else {
+    LatticeArgs<float> A = m.a;
+    if (FORCED) {
+      const float* Fr = ftab + m.ftab_off + 3LL * substep;
+      A.F[0] = Fr[0];
+      A.F[1] = Fr[1];
+      A.F[2] = Fr[2];
+    }
+    if (phase == 0)
+      node_step_any<Q, ST_F16, MODE_AA_EVEN, FORCED>(A, x, y, z);
+    else
+      node_step_any<Q, ST_F16, MODE_AA_ODD, FORCED>(A, x, y, z);
+  }
+}
+
+__device__ __forceinline__ int find_member(const BatchMember* __restrict__ ms, int nm,
+                                           long long tile) {
+  int lo = 0, hi = nm - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ms[mid].tile_begin <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_batch_step(const BatchMember* __restrict__ ms, int nm,
+                                                    const float* __restrict__ ftab, int substep) {
+  const long long tile = blockIdx.x;
+  const int mi = find_member(ms, nm, tile);
+  const BatchMember& m = ms[mi];
+  if (substep >= m.steps) return;  // this member's budget is used up
+  const long long lt = tile - m.tile_begin;
+  if (lt >= m.ntiles) return;
+  const int tx = m.a.tx, ty = m.a.ty;
+  const int t = threadIdx.x;
+  if (t >= tx * ty) return;
+  const int bx = (int)(lt % m.a.tiles_x);
+  const long long r = lt / m.a.tiles_x;
+  const int by = (int)(r % m.a.tiles_y);
+  const int z = (int)(r / m.a.tiles_y);
+  const int x = bx * tx + t % tx;
+  const int y = by * ty + t / tx;
+  if (x >= m.a.nx || y >= m.a.ny) return;
+  const int phase = (m.phase0 + substep) & 1;
+  if (m.q == 14) {
+    if (m.storage == ST_F32) {
+      if (m.forced)
+        batch_node<14, ST_F32, true>(m, phase, ftab, substep, x, y, z);
+      else
+        batch_node<14, ST_F32, false>(m, phase, ftab, substep, x, y, z);
+    } else {
+      if (m.forced)
+        batch_node<14, ST_F16, true>(m, phase, ftab, substep, x, y, z);
+      else
+        batch_node<14, ST_F16, false>(m, phase, ftab, substep, x, y, z);
+    }
+  } else {
+    if (m.storage == ST_F32) {
+      if (m.forced)
+        batch_node<18, ST_F32, true>(m, phase, ftab, substep, x, y, z);
+      else
+        batch_node<18, ST_F32, false>(m, phase, ftab, substep, x, y, z);
+    } else {
+      if (m.forced)
+        batch_node<18, ST_F16, true>(m, phase, ftab, substep, x, y, z);
+      else
+        batch_node<18, ST_F16, false>(m, phase, ftab, substep, x, y, z);
+    }
+  }
+}
+
+hipError_t launch_batch_step(const BatchMember* ms, int nm, long long total_tiles,
+                             const float* ftab, int substep, hipStream_t s) {
+  clear_stale_error();
+  if (nm <= 0 || total_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_step, dim3((unsigned)total_tiles), dim3(256), 0, s, ms, nm, ftab,
+                     substep);
+  return hipGetLastError();
+}
+
+// Batched monitor: block b belongs to the member whose block range holds it.
+__device__ __forceinline__ int find_block_member(const long long* __restrict__ bb, int nm,
+                                                 long long blk) {
+  int lo = 0, hi = nm - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bb[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_batch_monitor(const BatchMember* __restrict__ ms, int nm,
+                                                       void* const* __restrict__ snaps,
+                                                       double* __restrict__ partial,
+                                                       const long long* __restrict__ pofs,
+                                                       const long long* __restrict__ bbeg,
+                                                       const int* __restrict__ phases) {
+  const long long blk = blockIdx.x;
+  const int mi = find_block_member(bbeg, nm, blk);
+  const BatchMember& m = ms[mi];
+  const int lb = (int)(blk - bbeg[mi]);
+  const int nblk = (int)((mi + 1 < nm ? bbeg[mi + 1] : (long long)gridDim.x) - bbeg[mi]);
+  const int ph = phases[mi];
+  double a = 0, b = 0, c = 0;
+  float* snap = static_cast<float*>(snaps[mi]);
+  LatticeArgs<float> A = m.a;
+  if (m.q == 14) {
+    if (m.storage == ST_F32) {
+      if (ph == 0) monitor_body<14, ST_F32, 0>(A, snap, lb, nblk, a, b, c);
+      else monitor_body<14, ST_F32, 1>(A, snap, lb, nblk, a, b, c);
+    } else {
+      if (ph == 0) monitor_body<14, ST_F16, 0>(A, snap, lb, nblk, a, b, c);
+      else monitor_body<14, ST_F16, 1>(A, snap, lb, nblk, a, b, c);
+    }
+  } else {
+    if (m.storage == ST_F32) {
+      if (ph == 0) monitor_body<18, ST_F32, 0>(A, snap, lb, nblk, a, b, c);
+      else monitor_body<18, ST_F32, 1>(A, snap, lb, nblk, a, b, c);
+    } else {
+      if (ph == 0) monitor_body<18, ST_F16, 0>(A, snap, lb, nblk, a, b, c);
+      else monitor_body<18, ST_F16, 1>(A, snap, lb, nblk, a, b, c);
+    }
+  }
+  if (threadIdx.x == 0) {
+    double* o = partial + 3 * (pofs[mi] + lb);
+    o[0] = a;
+    o[1] = b;
+    o[2] = c;
+  }
+}
+
+hipError_t launch_batch_monitor(const BatchMember* ms, int nm, void* const* snaps, double* partial,
+                                const long long* pofs, long long total_blocks,
+                                const long long* bbeg, const int* phases, hipStream_t s) {
+  clear_stale_error();
+  if (nm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_monitor, dim3((unsigned)total_blocks), dim3(256), 0, s, ms, nm, snaps,
+                     partial, pofs, bbeg, phases);
+  return hipGetLastError();
+}
+
+// One workgroup per member: fixed-order sum of that member's partials.
+__global__ __launch_bounds__(256) void k_batch_reduce(const double* __restrict__ partial,
+                                                      const long long* __restrict__ pofs,
+                                                      const long long* __restrict__ pcount,
+                                                      double* __restrict__ out) {
+  const int mi = blockIdx.x;
+  const double* p = partial + 3 * pofs[mi];
+  const long long nb = pcount[mi];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (long long i = threadIdx.x; i < nb; i += 256) {
+    a += p[3 * i];
+    b += p[3 * i + 1];
+    c += p[3 * i + 2];
+  }
+  block_sum3(a, b, c);
+  if (threadIdx.x == 0) {
+    out[3 * mi] = a;
+    out[3 * mi + 1] = b;
+    out[3 * mi + 2] = c;
+  }
+}
+
+hipError_t launch_batch_reduce(const double* partial, const long long* pofs,
+                               const long long* pcount, int nm, double* out, hipStream_t s) {
+  clear_stale_error();
+  if (nm <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_reduce, dim3(nm), dim3(256), 0, s, partial, pofs, pcount, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,85 @@
+// kernels.hpp -- argument blocks and launch entry points of the device
+// code (kernels.hip); used by the host runtime (runtime.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace lbm {
+
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
+// AB: read natural A, collide, push into B.  AA_EVEN: read natural, write
+// each post-collision population into its opposite slot of the same node.
+// AA_ODD: gather from the neighbours' opposite slots, collide, push.
+enum Mode { MODE_AB = 0, MODE_AA_EVEN = 1, MODE_AA_ODD = 2 };
+
+// Everything a lattice kernel needs about one lattice, in compute type C.
+template <typename C> struct LatticeArgs {
+  void* f;                 // populations (AB: the copy read this step)
+  void* g;                 // AB: the copy written this step; AA: == f
+  long long stride;        // elements between population arrays (= N)
+  int nx, ny, nz;
+  int per_x, per_y, per_z; // periodic axes
+  int tx, ty, tiles_x, tiles_y;  // x-y tile of one workgroup
+  C sN[18], hN[18];        // s_k/N_k, (1 - s_k/2)/N_k
+  C bb[18][3];             // 6 w_a (c_a . u_w) for link a leaving through
+                           // the x / y / z face it crosses
+  C F[3];                  // body force at this step
+  C base[18];              // FP16 deviation base 3 w_a p0
+  C scale, inv_scale;      // FP16 2^s, 2^-s
+};
+
+// Launches (all asynchronous on `stream`; return a hipError_t).
+hipError_t launch_step(int q, int storage, int mode, bool forced, const void* args,
+                       size_t args_bytes, hipStream_t stream);
+// Decode population a of the current state (phase: 0 natural, 1 AA
+// swapped) into FP64 out[N].
+hipError_t launch_get_pop(int q, int storage, int phase, int a, const void* args, double* out,
+                          hipStream_t stream);
+// Encode FP64 in[N] into population a (natural layout).
+hipError_t launch_set_pop(int q, int storage, int a, const void* args, const double* in,
+                          hipStream_t stream);
+// f = f_eq(p, u - F/2) (FP64 arithmetic) from device p[N], u[3][N] or, when
+// p/u are NULL, the uniform p0/u0; written in natural layout.
+hipError_t launch_init_eq(int q, int storage, const void* args, const double* p, const double* u,
+                          double p0, const double* u0, hipStream_t stream);
+// p[N], u[3][N] (FP64) of the current state with the force args.F.
+hipError_t launch_macros(int q, int storage, int phase, const void* args, double* p, double* u,
+                         hipStream_t stream);
+// Monitor pass 1: per-block FP64 partial sums of sum|u - snap|, sum|u|,
+// sum P into partial[3*nblocks]; refreshes snap (compute type) with u.
+// nblocks is returned through *nblocks_out (host computed).
+hipError_t launch_monitor(int q, int storage, int phase, const void* args, void* snap,
+                          double* partial, int* nblocks_out, hipStream_t stream);
+// Monitor pass 2: fixed-order sum of the partials into out[3].
+hipError_t launch_reduce_partials(const double* partial, int nblocks, double* out,
+                                  hipStream_t stream);
+int monitor_blocks(long long nodes);
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+// ---- batched execution -------------------------------------------------
+// One member of a batch, as the batched kernel sees it (FP32 compute).
+struct BatchMember {
+  LatticeArgs<float> a;    // a.F unused: forces come from the F table
+  int q, storage;
+  int phase0;              // AA parity at substep 0
+  int steps;               // substeps this member takes in this launch set
+  long long tile_begin;    // first global tile index of this member
+  long long ntiles;
+  long long ftab_off;      // float offset of this member's F(t) rows (3 per substep)
+  int forced;
+  int pad_;
+};
+// One time step (substep s of the current quantum) of every member.
+hipError_t launch_batch_step(const BatchMember* members, int nmembers, long long total_tiles,
+                             const float* ftab, int substep, hipStream_t stream);
+// Monitor pass 1 of every member: partial sums into partial[3*blocks of
+// member]; member m writes at partial + 3*pofs[m].
+hipError_t launch_batch_monitor(const BatchMember* members, int nmembers, void* const* snaps,
+                                double* partial, const long long* pofs, long long total_blocks,
+                                const long long* block_begin, const int* phases,
+                                hipStream_t stream);
+hipError_t launch_batch_reduce(const double* partial, const long long* pofs,
+                               const long long* pcount, int nmembers, double* out,
+                               hipStream_t stream);
+
+}  // namespace lbm

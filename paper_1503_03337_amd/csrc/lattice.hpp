@@ -1,0 +1,319 @@
+// lattice.hpp -- compile-time lattices and the MRT collision of the
+// incompressible D3Q14 / D3Q18 models (arXiv 1503.03337, Sec. 3 and
+// Appendix B), written for gfx950.
+//
+// The transforms m = T f and f* = f - T' N^-1 D are not stored as matrices:
+// both T's factor into sums/differences of opposite axis pairs and small
+// Walsh-Hadamard butterflies over the diagonal velocities (the 8 corners of
+// q = 14 form one 3-level butterfly; the 12 edges of q = 18 form three
+// 2-level ones, one per coordinate plane).  Each moment below is written as
+// a combination of those partial sums; the combinations follow the rows of
+// Eq. (T14) and of the 18x18 T of Appendix B.  No MFMA: every entry of T is
+// a small integer, so the transform is ~100-170 add/sub per node.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+template <int Q> struct Lattice;
+
+// Sec. 3: six axis velocities, then the eight corners, x sign fastest.
+template <> struct Lattice<14> {
+  static constexpr int q = 14;
+  static constexpr int cx[14] = {1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+  static constexpr int cy[14] = {0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+  static constexpr int cz[14] = {0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+  static constexpr int opp[14] = {1, 0, 3, 2, 5, 4, 13, 12, 11, 10, 9, 8, 7, 6};
+  // D3Q15 weights without the rest velocity (rest weight 2/9).
+  static constexpr double w_axis = 1.0 / 9.0, w_diag = 1.0 / 72.0, w0 = 2.0 / 9.0;
+  // squared row norms of T (T T' = diag(N))
+  static constexpr int N[14] = {14, 168, 10, 40, 10, 40, 10, 40, 12, 4, 8, 8, 8, 8};
+};
+
+// Appendix B: six axis velocities, then the xy, xz and yz edges.
+template <> struct Lattice<18> {
+  static constexpr int q = 18;
+  static constexpr int cx[18] = {1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[18] = {0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[18] = {0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+  static constexpr int opp[18] = {1, 0, 3, 2, 5, 4, 9, 8, 7, 6, 13, 12, 11, 10, 17, 16, 15, 14};
+  static constexpr double w_axis = 1.0 / 18.0, w_diag = 1.0 / 36.0, w0 = 1.0 / 3.0;
+  static constexpr int N[18] = {18, 36, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+};
+
+template <int Q>
+__host__ __device__ constexpr double weight(int a) {
+  return (Lattice<Q>::cx[a] * Lattice<Q>::cx[a] + Lattice<Q>::cy[a] * Lattice<Q>::cy[a] +
+          Lattice<Q>::cz[a] * Lattice<Q>::cz[a]) == 1
+             ? Lattice<Q>::w_axis
+             : Lattice<Q>::w_diag;
+}
+
+// Per-moment relaxation coefficients, pre-divided by the row norms:
+//   sN_k = s_k / N_k,   hN_k = (1 - s_k/2) / N_k,
+// so that d_k = D_k / N_k = sN_k (m_k - meq_k) - hN_k mF_k.
+template <typename C> struct Relax {
+  C sN[18];
+  C hN[18];
+};
+
+// ---------------------------------------------------------------------------
+// 14-velocity model.  Moments (Eq. (moment)):
+//   0 P, 1 e, 2 jx, 3 qx, 4 jy, 5 qy, 6 jz, 7 qz, 8 3pxx, 9 pww, 10 pxy,
+//   11 pyz, 12 pxz, 13 txyz.
+// ---------------------------------------------------------------------------
+template <typename C, bool FORCED>
+__device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C (&F)[3]) {
+  // forward: axis pairs
+  const C ax = f[0] + f[1], dx = f[0] - f[1];
+  const C ay = f[2] + f[3], dy = f[2] - f[3];
+  const C az = f[4] + f[5], dz = f[4] - f[5];
+  const C A = ax + ay + az;
+  // forward: corner butterfly (x, then y, then z)
+  const C cs1 = f[6] + f[7], cd1 = f[6] - f[7];
+  const C cs2 = f[8] + f[9], cd2 = f[8] - f[9];
+  const C cs3 = f[10] + f[11], cd3 = f[10] - f[11];
+  const C cs4 = f[12] + f[13], cd4 = f[12] - f[13];
+  const C pp = cs1 + cs2, py = cs1 - cs2, px = cd1 + cd2, pxy = cd1 - cd2;  // z = +1 layer
+  const C mp = cs3 + cs4, my = cs3 - cs4, mx = cd3 + cd4, mxy = cd3 - cd4;  // z = -1 layer
+  const C K0 = pp + mp, Kz = pp - mp, Ky = py + my, Kyz = py - my;
+  const C Kx = px + mx, Kxz = px - mx, Kxy = pxy + mxy, Kxyz = pxy - mxy;
+
+  const C mP = A + K0;
+  const C me = C(3) * K0 - C(4) * A;
+  const C jx = dx + Kx, qx = Kx - C(4) * dx;
+  const C jy = dy + Ky, qy = Ky - C(4) * dy;
+  const C jz = dz + Kz, qz = Kz - C(4) * dz;
+  const C pxx3 = C(2) * ax - ay - az;
+  const C pww = ay - az;
+
+  // Eq. (hgl): u = j + F/2, p = 3/7 (P - |u|^2/3)
+  C ux = jx, uy = jy, uz = jz;
+  if (FORCED) {
+    ux += C(0.5) * F[0];
+    uy += C(0.5) * F[1];
+    uz += C(0.5) * F[2];
+  }
+  const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const C usq = uxx + uyy + uzz;
+  const C p = (mP - usq * C(1.0 / 3.0)) * C(3.0 / 7.0);
+
+  // d_k = sN_k (m_k - meq_k) - hN_k mF_k, Eq. (meq) equilibria
+  C d0 = r.sN[0] * (mP - (C(7.0 / 3.0) * p + usq * C(1.0 / 3.0)));
+  C d1e = r.sN[1] * (me - (usq - C(7) * p));
+  C d2 = r.sN[2] * (jx - ux);
+  C d3 = r.sN[3] * (qx + C(7.0 / 3.0) * ux);
+  C d4 = r.sN[4] * (jy - uy);
+  C d5 = r.sN[5] * (qy + C(7.0 / 3.0) * uy);
+  C d6 = r.sN[6] * (jz - uz);
+  C d7 = r.sN[7] * (qz + C(7.0 / 3.0) * uz);
+  C d8 = r.sN[8] * (pxx3 - (C(3) * uxx - usq));
+  C d9 = r.sN[9] * (pww - (uyy - uzz));
+  C d10 = r.sN[10] * (Kxy - ux * uy);
+  C d11 = r.sN[11] * (Kyz - uy * uz);
+  C d12 = r.sN[12] * (Kxz - ux * uz);
+  C d13 = r.sN[13] * Kxyz;
+  if (FORCED) {
+    // m_F = (d m_eq / d u) . F
+    const C Fx = F[0], Fy = F[1], Fz = F[2];
+    const C w = ux * Fx + uy * Fy + uz * Fz;
+    d0 -= r.hN[0] * (C(2.0 / 3.0) * w);
+    d1e -= r.hN[1] * (C(2) * w);
+    d2 -= r.hN[2] * Fx;
+    d3 -= r.hN[3] * (C(-7.0 / 3.0) * Fx);
+    d4 -= r.hN[4] * Fy;
+    d5 -= r.hN[5] * (C(-7.0 / 3.0) * Fy);
+    d6 -= r.hN[6] * Fz;
+    d7 -= r.hN[7] * (C(-7.0 / 3.0) * Fz);
+    d8 -= r.hN[8] * (C(6) * ux * Fx - C(2) * w);
+    d9 -= r.hN[9] * (C(2) * (uy * Fy - uz * Fz));
+    d10 -= r.hN[10] * (ux * Fy + uy * Fx);
+    d11 -= r.hN[11] * (uy * Fz + uz * Fy);
+    d12 -= r.hN[12] * (ux * Fz + uz * Fx);
+  }
+
+  // back-transform f*_a = f_a - sum_k T_ka d_k, axis velocities
+  const C bA = d0 - C(4) * d1e;
+  const C X = d2 - C(4) * d3, Y = d4 - C(4) * d5, Z = d6 - C(4) * d7;
+  const C t8 = C(2) * d8;
+  f[0] -= (bA + X) + t8;
+  f[1] -= (bA - X) + t8;
+  const C yy = d9 - d8, zz = -(d8 + d9);
+  f[2] -= (bA + Y) + yy;
+  f[3] -= (bA - Y) + yy;
+  f[4] -= (bA + Z) + zz;
+  f[5] -= (bA - Z) + zz;
+  // corners: inverse butterfly of W0 + cx Wx + cy Wy + cz Wz + cxcy Wxy + ...
+  const C W0 = d0 + C(3) * d1e;
+  const C Wx = d2 + d3, Wy = d4 + d5, Wz = d6 + d7;
+  const C zp0 = W0 + Wz, zpx = Wx + d12, zpy = Wy + d11, zpxy = d10 + d13;
+  const C zm0 = W0 - Wz, zmx = Wx - d12, zmy = Wy - d11, zmxy = d10 - d13;
+  C a = zp0 + zpy, b = zpx + zpxy;
+  f[6] -= a + b;
+  f[7] -= a - b;
+  a = zp0 - zpy;
+  b = zpx - zpxy;
+  f[8] -= a + b;
+  f[9] -= a - b;
+  a = zm0 + zmy;
+  b = zmx + zmxy;
+  f[10] -= a + b;
+  f[11] -= a - b;
+  a = zm0 - zmy;
+  b = zmx - zmxy;
+  f[12] -= a + b;
+  f[13] -= a - b;
+}
+
+// ---------------------------------------------------------------------------
+// 18-velocity model.  Moments (Eq. (d3q18moment)):
+//   0 P, 1 e, 2 jx, 3 qx, 4 jy, 5 qy, 6 jz, 7 qz, 8 3pxx, 9 3pixx, 10 pww,
+//   11 piww, 12 pxy, 13 pyz, 14 pxz, 15 tx, 16 ty, 17 tz.
+// ---------------------------------------------------------------------------
+template <typename C, bool FORCED>
+__device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C (&F)[3]) {
+  const C ax = f[0] + f[1], dx = f[0] - f[1];
+  const C ay = f[2] + f[3], dy = f[2] - f[3];
+  const C az = f[4] + f[5], dz = f[4] - f[5];
+  const C A = ax + ay + az;
+  // xy edges 6..9 in (cx, cy): (+,+) (-,+) (+,-) (-,-)
+  C s = f[6] + f[7], d = f[6] - f[7], s_ = f[8] + f[9], d_ = f[8] - f[9];
+  const C Sxy = s + s_, Yxy = s - s_, Xxy = d + d_, XYxy = d - d_;
+  // xz edges 10..13 in (cx, cz)
+  s = f[10] + f[11];
+  d = f[10] - f[11];
+  s_ = f[12] + f[13];
+  d_ = f[12] - f[13];
+  const C Sxz = s + s_, Zxz = s - s_, Xxz = d + d_, XZxz = d - d_;
+  // yz edges 14..17 in (cy, cz)
+  s = f[14] + f[15];
+  d = f[14] - f[15];
+  s_ = f[16] + f[17];
+  d_ = f[16] - f[17];
+  const C Syz = s + s_, Zyz = s - s_, Yyz = d + d_, YZyz = d - d_;
+
+  const C E = Sxy + Sxz + Syz;
+  const C mP = A + E;
+  const C me = E - C(2) * A;
+  const C ex = Xxy + Xxz, ey = Yxy + Yyz, ez = Zxz + Zyz;
+  const C jx = dx + ex, qx = ex - C(4) * dx;
+  const C jy = dy + ey, qy = ey - C(4) * dy;
+  const C jz = dz + ez, qz = ez - C(4) * dz;
+  const C axis_xx = C(2) * ax - ay - az;
+  const C edge_xx = (Sxy + Sxz) - C(2) * Syz;
+  const C pxx3 = axis_xx + edge_xx;
+  const C pixx3 = edge_xx - C(2) * axis_xx;
+  const C axis_ww = ay - az, edge_ww = Sxy - Sxz;
+  const C pww = axis_ww + edge_ww;
+  const C piww = edge_ww - C(2) * axis_ww;
+  const C tx = Xxy - Xxz, ty = Yyz - Yxy, tz = Zxz - Zyz;
+
+  C ux = jx, uy = jy, uz = jz;
+  if (FORCED) {
+    ux += C(0.5) * F[0];
+    uy += C(0.5) * F[1];
+    uz += C(0.5) * F[2];
+  }
+  const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const C usq = uxx + uyy + uzz;
+  // Eq. (hgl) with w0 = 1/3: p = (P - |u|^2/2) / 2
+  const C p = (mP - C(0.5) * usq) * C(0.5);
+  const C qxx = C(3) * uxx - usq, qww = uyy - uzz;
+
+  C d0 = r.sN[0] * (mP - (C(2) * p + C(0.5) * usq));
+  C d1e = r.sN[1] * (me - (C(0.5) * usq - p));
+  C d2 = r.sN[2] * (jx - ux);
+  C d3 = r.sN[3] * (qx + C(2.0 / 3.0) * ux);
+  C d4 = r.sN[4] * (jy - uy);
+  C d5 = r.sN[5] * (qy + C(2.0 / 3.0) * uy);
+  C d6 = r.sN[6] * (jz - uz);
+  C d7 = r.sN[7] * (qz + C(2.0 / 3.0) * uz);
+  C d8 = r.sN[8] * (pxx3 - qxx);
+  C d9 = r.sN[9] * (pixx3 + C(0.5) * qxx);
+  C d10 = r.sN[10] * (pww - qww);
+  C d11 = r.sN[11] * (piww + C(0.5) * qww);
+  C d12 = r.sN[12] * (XYxy - ux * uy);
+  C d13 = r.sN[13] * (YZyz - uy * uz);
+  C d14 = r.sN[14] * (XZxz - ux * uz);
+  C d15 = r.sN[15] * tx;
+  C d16 = r.sN[16] * ty;
+  C d17 = r.sN[17] * tz;
+  if (FORCED) {
+    const C Fx = F[0], Fy = F[1], Fz = F[2];
+    const C w = ux * Fx + uy * Fy + uz * Fz;
+    const C gxx = C(6) * ux * Fx - C(2) * w;
+    const C gww = uy * Fy - uz * Fz;
+    d0 -= r.hN[0] * w;
+    d1e -= r.hN[1] * w;
+    d2 -= r.hN[2] * Fx;
+    d3 -= r.hN[3] * (C(-2.0 / 3.0) * Fx);
+    d4 -= r.hN[4] * Fy;
+    d5 -= r.hN[5] * (C(-2.0 / 3.0) * Fy);
+    d6 -= r.hN[6] * Fz;
+    d7 -= r.hN[7] * (C(-2.0 / 3.0) * Fz);
+    d8 -= r.hN[8] * gxx;
+    d9 -= r.hN[9] * (C(-0.5) * gxx);
+    d10 -= r.hN[10] * (C(2) * gww);
+    d11 -= r.hN[11] * (-gww);
+    d12 -= r.hN[12] * (ux * Fy + uy * Fx);
+    d13 -= r.hN[13] * (uy * Fz + uz * Fy);
+    d14 -= r.hN[14] * (ux * Fz + uz * Fx);
+  }
+
+  // back-transform, axis velocities (columns 1..6 of T)
+  const C bA = d0 - C(2) * d1e;
+  const C X = d2 - C(4) * d3, Y = d4 - C(4) * d5, Z = d6 - C(4) * d7;
+  const C xx = C(2) * d8 - C(4) * d9;
+  const C yz_common = C(2) * d9 - d8;  // -d8 + 2 d9
+  const C ww = d10 - C(2) * d11;
+  const C yy = yz_common + ww, zz = yz_common - ww;
+  f[0] -= (bA + X) + xx;
+  f[1] -= (bA - X) + xx;
+  f[2] -= (bA + Y) + yy;
+  f[3] -= (bA - Y) + yy;
+  f[4] -= (bA + Z) + zz;
+  f[5] -= (bA - Z) + zz;
+  // edges: value(s1,s2) = W0 + s1 W1 + s2 W2 + s1 s2 W12 per plane
+  const C E0 = d0 + d1e, G = d8 + d9, H = d10 + d11;
+  const C jqx = d2 + d3, jqy = d4 + d5, jqz = d6 + d7;
+  {  // xy plane (cx, cy)
+    const C W0 = E0 + G + H, W1 = jqx + d15, W2 = jqy - d16, W12 = d12;
+    C a = W0 + W2, b = W1 + W12;
+    f[6] -= a + b;
+    f[7] -= a - b;
+    a = W0 - W2;
+    b = W1 - W12;
+    f[8] -= a + b;
+    f[9] -= a - b;
+  }
+  {  // xz plane (cx, cz)
+    const C W0 = E0 + G - H, W1 = jqx - d15, W2 = jqz + d17, W12 = d14;
+    C a = W0 + W2, b = W1 + W12;
+    f[10] -= a + b;
+    f[11] -= a - b;
+    a = W0 - W2;
+    b = W1 - W12;
+    f[12] -= a + b;
+    f[13] -= a - b;
+  }
+  {  // yz plane (cy, cz)
+    const C W0 = E0 - C(2) * G, W1 = jqy + d16, W2 = jqz - d17, W12 = d13;
+    C a = W0 + W2, b = W1 + W12;
+    f[14] -= a + b;
+    f[15] -= a - b;
+    a = W0 - W2;
+    b = W1 - W12;
+    f[16] -= a + b;
+    f[17] -= a - b;
+  }
+}
+
+template <int Q, typename C, bool FORCED>
+__device__ __forceinline__ void collide(C (&f)[Q], const Relax<C>& r, const C (&F)[3]) {
+  if constexpr (Q == 14)
+    collide14<C, FORCED>(f, r, F);
+  else
+    collide18<C, FORCED>(f, r, F);
+}
+
+}  // namespace lbm

@@ -1,0 +1,874 @@
+// runtime.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// Owns contexts (one lattice each), their device memory, the host step
+// loop, the FP64 monitors and batches.  Every entry point validates its
+// arguments, returns an lbm_status and records a message; no exception
+// crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int bytes_of(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F32 ? 4 : 2; }
+
+// Monitor scratch: velocity snapshot (3 N values of the compute type),
+// per-block partial sums and the 3 final sums.
+size_t monitor_bytes(size_t N, int storage) {
+  const size_t snap = 3 * N * (storage == LBM_F64 ? 8 : 4);
+  return align_up(snap) + align_up(3 * sizeof(double) * 2048) + align_up(4 * sizeof(double));
+}
+
+size_t population_bytes(int q, size_t N, int storage) {
+  return (size_t)q * N * (size_t)bytes_of(storage);
+}
+
+std::string validate(int model, int nx, int ny, int nz, const double* s, const lbm_spec* sp) {
+  if (model != 14 && model != 18) return "model must be 14 or 18";
+  if (nx < 1 || ny < 1 || nz < 1) return "lattice dimensions must be >= 1";
+  const long long N = (long long)nx * ny * nz;
+  if (N >= (1LL << 31)) return "lattice too large (nx*ny*nz must be < 2^31)";
+  if (!sp) return "spec is NULL";
+  if (sp->storage < LBM_F64 || sp->storage > LBM_F16DEV) return "unknown storage";
+  if (sp->pattern != LBM_AB && sp->pattern != LBM_AA) return "unknown pattern";
+  if (sp->storage == LBM_F16DEV && (sp->f16_scale_log2 < 0 || sp->f16_scale_log2 > 24))
+    return "f16_scale_log2 must be in 0..24";
+  if (sp->monitor_every < 0) return "monitor_every must be >= 0";
+  for (int d = 0; d < 3; ++d) {
+    const int a = sp->face[2 * d], b = sp->face[2 * d + 1];
+    if ((a != LBM_PERIODIC && a != LBM_WALL) || (b != LBM_PERIODIC && b != LBM_WALL))
+      return "face kind must be LBM_PERIODIC or LBM_WALL";
+    if ((a == LBM_PERIODIC) != (b == LBM_PERIODIC)) return "periodic faces must come in pairs";
+  }
+  for (int f = 0; f < 6; ++f) {
+    const double* u = sp->wall_u[f];
+    const double m = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(m < 0.3)) return "wall speed must be < 0.3 (lattice units)";
+  }
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(sp->F0[d]) || !std::isfinite(sp->FA[d])) return "force must be finite";
+  if (!std::isfinite(sp->p0)) return "p0 must be finite";
+  if (s) {
+    for (int k = 0; k < model; ++k)
+      if (!(s[k] >= 0.0 && s[k] < 2.0)) return "relaxation rates must lie in [0, 2)";
+  } else {
+    return "s_vec is NULL";
+  }
+  return "";
+}
+
+// F(t) = F0 + FA cos(2 pi t / FT) (FT <= 0: F0).
+void force_at(const lbm_spec& sp, long long t, double F[3]) {
+  double ph = 1.0;
+  if (sp.FT > 0.0) ph = std::cos(2.0 * M_PI * (double)t / sp.FT);
+  for (int d = 0; d < 3; ++d) F[d] = sp.F0[d] + (sp.FT > 0.0 ? sp.FA[d] * ph : 0.0);
+}
+
+bool has_force(const lbm_spec& sp) {
+  for (int d = 0; d < 3; ++d)
+    if (sp.F0[d] != 0.0 || (sp.FT > 0.0 && sp.FA[d] != 0.0)) return true;
+  return false;
+}
+
+template <int Q>
+void lattice_tables(int (&cx)[18], int (&cy)[18], int (&cz)[18], double (&w)[18], int (&N)[18]) {
+  for (int a = 0; a < Q; ++a) {
+    cx[a] = Lattice<Q>::cx[a];
+    cy[a] = Lattice<Q>::cy[a];
+    cz[a] = Lattice<Q>::cz[a];
+    w[a] = weight<Q>(a);
+    N[a] = Lattice<Q>::N[a];
+  }
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  int q = 0, nx = 0, ny = 0, nz = 0;
+  size_t N = 0;
+  lbm_spec spec{};
+  double s[18] = {};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* buf = nullptr;
+  bool own_buf = false;
+  size_t footprint = 0;
+  void* popA = nullptr;  // current copy
+  void* popB = nullptr;  // AB: the other copy
+  int phase = 0;         // AA: 0 natural layout, 1 swapped
+  long long t = 0;
+  // monitor
+  void* mon_buf = nullptr;  // separately allocated monitor area (when not in buf)
+  void* snap = nullptr;
+  double* partial = nullptr;
+  double* d_res = nullptr;
+  bool snap_valid = false;
+  long long t_snap = 0;
+  long long mon_lag = 0;
+  bool mon_ran = false;
+  bool mon_pending = false;
+  double mon[3] = {0, 0, 0};
+  bool forced = false;
+  int tx = 1, ty = 1;
+  LatticeArgs<double> a64{};
+  LatticeArgs<float> a32{};
+  std::string err;
+  void* batch = nullptr;  // batch this context belongs to (or NULL)
+};
+
+namespace {
+
+// Message of the last failed lbm_create on this thread (lbm_last_error(NULL)).
+thread_local std::string g_create_err;
+
+int fail(lbm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
+  return fail(c, LBM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                               \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+template <typename C>
+void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
+  int cx[18], cy[18], cz[18], Nk[18];
+  double w[18];
+  if (c.q == 14)
+    lattice_tables<14>(cx, cy, cz, w, Nk);
+  else
+    lattice_tables<18>(cx, cy, cz, w, Nk);
+  std::memset(&A, 0, sizeof(A));
+  A.f = c.popA;
+  A.g = c.popB ? c.popB : c.popA;
+  A.stride = (long long)c.N;
+  A.nx = c.nx;
+  A.ny = c.ny;
+  A.nz = c.nz;
+  A.per_x = c.spec.face[0] == LBM_PERIODIC;
+  A.per_y = c.spec.face[2] == LBM_PERIODIC;
+  A.per_z = c.spec.face[4] == LBM_PERIODIC;
+  A.tx = c.tx;
+  A.ty = c.ty;
+  A.tiles_x = (c.nx + c.tx - 1) / c.tx;
+  A.tiles_y = (c.ny + c.ty - 1) / c.ty;
+  for (int k = 0; k < c.q; ++k) {
+    A.sN[k] = (C)(c.s[k] / Nk[k]);
+    A.hN[k] = (C)((1.0 - 0.5 * c.s[k]) / Nk[k]);
+  }
+  // Wall term of population a leaving through the face its d-component
+  // points at: 6 w_a (c_a . u_w), computed as the FP64 oracle of the paper
+  // would (w_a times 6, times the dot product).
+  for (int a = 0; a < c.q; ++a) {
+    const int comp[3] = {cx[a], cy[a], cz[a]};
+    for (int d = 0; d < 3; ++d) {
+      A.bb[a][d] = 0;
+      if (!comp[d]) continue;
+      const int face = 2 * d + (comp[d] > 0 ? 1 : 0);
+      const double* uw = c.spec.wall_u[face];
+      const double cu = cx[a] * uw[0] + cy[a] * uw[1] + cz[a] * uw[2];
+      A.bb[a][d] = (C)(6.0 * w[a] * cu);
+    }
+    A.base[a] = (C)(3.0 * w[a] * c.spec.p0);
+  }
+  const double sc = std::ldexp(1.0, c.spec.f16_scale_log2);
+  A.scale = (C)sc;
+  A.inv_scale = (C)(1.0 / sc);
+  A.F[0] = A.F[1] = A.F[2] = 0;
+}
+
+void refresh_args(lbm_ctx& c) {
+  fill_args<double>(c, c.a64);
+  fill_args<float>(c, c.a32);
+}
+
+const void* args_ptr(lbm_ctx& c) {
+  return c.spec.storage == LBM_F64 ? (const void*)&c.a64 : (const void*)&c.a32;
+}
+
+void set_force(lbm_ctx& c, long long t) {
+  double F[3];
+  force_at(c.spec, t, F);
+  for (int d = 0; d < 3; ++d) {
+    c.a64.F[d] = F[d];
+    c.a32.F[d] = (float)F[d];
+  }
+}
+
+void pick_tile(int nx, int ny, int& tx, int& ty) {
+  if (nx >= 256) {
+    tx = 256;
+    ty = 1;
+  } else {
+    tx = nx;
+    ty = std::max(1, std::min(ny, 256 / nx));
+  }
+}
+
+int ensure_monitor(lbm_ctx* c) {
+  if (c->snap) return LBM_OK;
+  const size_t snap_b = align_up(3 * c->N * (c->spec.storage == LBM_F64 ? 8 : 4));
+  const size_t part_b = align_up(3 * sizeof(double) * 2048);
+  const size_t bytes = monitor_bytes(c->N, c->spec.storage);
+  char* base = nullptr;
+  HIPCHK(c, hipMalloc((void**)&base, bytes));
+  c->mon_buf = base;
+  c->snap = base;
+  c->partial = (double*)(base + snap_b);
+  c->d_res = (double*)(base + snap_b + part_b);
+  return LBM_OK;
+}
+
+int run_monitor(lbm_ctx* c) {
+  int rc = ensure_monitor(c);
+  if (rc) return rc;
+  set_force(*c, c->t);
+  int nb = 0;
+  const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
+  HIPCHK(c, launch_monitor(c->q, c->spec.storage, phase, args_ptr(*c), c->snap, c->partial, &nb,
+                           c->stream));
+  HIPCHK(c, launch_reduce_partials(c->partial, nb, c->d_res, c->stream));
+  c->mon_lag = c->snap_valid ? c->t - c->t_snap : 0;
+  c->snap_valid = true;
+  c->t_snap = c->t;
+  c->mon_ran = true;
+  c->mon_pending = true;
+  return LBM_OK;
+}
+
+int fetch_monitor(lbm_ctx* c) {
+  if (!c->mon_pending) return LBM_OK;
+  HIPCHK(c, hipMemcpyAsync(c->mon, c->d_res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->mon_pending = false;
+  return LBM_OK;
+}
+
+// RAII device scratch for the non-hot host-data paths.
+struct DevTmp {
+  void* p = nullptr;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void lbm_spec_default(lbm_spec* sp) {
+  if (!sp) return;
+  std::memset(sp, 0, sizeof(*sp));
+  for (int f = 0; f < 6; ++f) sp->face[f] = LBM_WALL;
+  sp->storage = LBM_F32;
+  sp->pattern = LBM_AA;
+  sp->f16_scale_log2 = 12;
+}
+
+size_t lbm_footprint_bytes(int model, int nx, int ny, int nz, const lbm_spec* sp) {
+  double s[18];
+  for (int k = 0; k < 18; ++k) s[k] = 1.0;
+  if (!validate(model, nx, ny, nz, s, sp).empty()) return 0;
+  const size_t N = (size_t)nx * ny * nz;
+  size_t b = align_up(population_bytes(model, N, sp->storage));
+  if (sp->pattern == LBM_AB) b *= 2;
+  if (sp->monitor_every > 0) b += monitor_bytes(N, sp->storage);
+  return b;
+}
+
+int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz, const double* s_vec,
+               const lbm_spec* sp) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  g_create_err.clear();
+  const std::string v = validate(model, nx, ny, nz, s_vec, sp);
+  if (!v.empty()) {
+    g_create_err = v;
+    return LBM_EINVAL;
+  }
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->q = model;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->N = (size_t)nx * ny * nz;
+  c->spec = *sp;
+  for (int k = 0; k < model; ++k) c->s[k] = s_vec[k];
+  c->stream = (hipStream_t)sp->stream;
+  c->forced = has_force(c->spec);
+  pick_tile(nx, ny, c->tx, c->ty);
+  (void)hipGetDevice(&c->device);
+  const size_t need = lbm_footprint_bytes(model, nx, ny, nz, sp);
+  c->footprint = need;
+  char* base = nullptr;
+  if (sp->dev_buf) {
+    if (sp->dev_buf_bytes < need) {
+      delete c;
+      g_create_err = "dev_buf_bytes below the footprint";
+      return LBM_ENOMEM;
+    }
+    if (((uintptr_t)sp->dev_buf) % kAlign != 0) {
+      delete c;
+      g_create_err = "dev_buf must be 256-byte aligned";
+      return LBM_EINVAL;
+    }
+    base = (char*)sp->dev_buf;
+    c->own_buf = false;
+  } else {
+    const hipError_t me = hipMalloc((void**)&base, need);
+    if (me != hipSuccess) {
+      (void)hipGetLastError();
+      delete c;
+      g_create_err = std::string("hipMalloc: ") + hipGetErrorString(me);
+      return LBM_ENOMEM;
+    }
+    c->own_buf = true;
+  }
+  c->buf = base;
+  const size_t pop = align_up(population_bytes(model, c->N, sp->storage));
+  c->popA = base;
+  c->popB = sp->pattern == LBM_AB ? base + pop : nullptr;
+  size_t off = pop * (sp->pattern == LBM_AB ? 2 : 1);
+  if (sp->monitor_every > 0) {
+    const size_t snap_b = align_up(3 * c->N * (sp->storage == LBM_F64 ? 8 : 4));
+    const size_t part_b = align_up(3 * sizeof(double) * 2048);
+    c->snap = base + off;
+    c->partial = (double*)(base + off + snap_b);
+    c->d_res = (double*)(base + off + snap_b + part_b);
+  }
+  refresh_args(*c);
+  set_force(*c, 0);
+  const double u0[3] = {sp->u0[0], sp->u0[1], sp->u0[2]};
+  hipError_t e = launch_init_eq(c->q, sp->storage, args_ptr(*c), nullptr, nullptr, sp->p0, u0,
+                                c->stream);
+  if (e != hipSuccess) {
+    g_create_err = std::string("initialisation kernel: ") + hipGetErrorString(e);
+    lbm_destroy(c);
+    return LBM_EDEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, long long n) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+  const int K = c->spec.monitor_every;
+  for (long long i = 0; i < n; ++i) {
+    set_force(*c, c->t);
+    int mode;
+    if (c->spec.pattern == LBM_AB) {
+      mode = MODE_AB;
+    } else {
+      mode = c->phase == 0 ? MODE_AA_EVEN : MODE_AA_ODD;
+    }
+    HIPCHK(c, launch_step(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), 0, c->stream));
+    if (c->spec.pattern == LBM_AB) {
+      std::swap(c->popA, c->popB);
+      c->a64.f = c->a32.f = c->popA;
+      c->a64.g = c->a32.g = c->popB;
+    } else {
+      c->phase ^= 1;
+    }
+    c->t += 1;
+    if (K > 0 && c->t % K == 0) {
+      const int rc = run_monitor(c);
+      if (rc) return rc;
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_macros_device(lbm_ctx* c, double* p_dev, double* u_dev) {
+  if (!c) return LBM_EINVAL;
+  set_force(*c, c->t);
+  const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
+  HIPCHK(c, launch_macros(c->q, c->spec.storage, phase, args_ptr(*c), p_dev, u_dev, c->stream));
+  return LBM_OK;
+}
+
+int lbm_macros(lbm_ctx* c, double* p, double* u) {
+  if (!c) return LBM_EINVAL;
+  if (!p && !u) return LBM_OK;
+  DevTmp tp, tu;
+  if (p) HIPCHK(c, hipMalloc(&tp.p, c->N * sizeof(double)));
+  if (u) HIPCHK(c, hipMalloc(&tu.p, 3 * c->N * sizeof(double)));
+  int rc = lbm_macros_device(c, (double*)tp.p, (double*)tu.p);
+  if (rc) return rc;
+  if (p)
+    HIPCHK(c, hipMemcpyAsync(p, tp.p, c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (u)
+    HIPCHK(c, hipMemcpyAsync(u, tu.p, 3 * c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_monitor(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  return run_monitor(c);
+}
+
+int lbm_residual(lbm_ctx* c, double* r) {
+  if (!c || !r) return LBM_EINVAL;
+  if (!c->mon_ran) return fail(c, LBM_ESTATE, "the monitor has not run");
+  int rc = fetch_monitor(c);
+  if (rc) return rc;
+  if (!std::isfinite(c->mon[0]) || !std::isfinite(c->mon[1]) || !std::isfinite(c->mon[2])) {
+    *r = std::numeric_limits<double>::quiet_NaN();
+    return fail(c, LBM_ENONFINITE, "monitor found a non-finite value");
+  }
+  if (c->mon_lag <= 0 || !(c->mon[1] > 0.0))
+    *r = std::numeric_limits<double>::infinity();
+  else
+    *r = c->mon[0] / ((double)c->mon_lag * c->mon[1]);
+  return LBM_OK;
+}
+
+int lbm_mass(lbm_ctx* c, double* m) {
+  if (!c || !m) return LBM_EINVAL;
+  if (!c->mon_ran) {
+    int rc = run_monitor(c);
+    if (rc) return rc;
+  }
+  int rc = fetch_monitor(c);
+  if (rc) return rc;
+  *m = c->mon[2];
+  if (!std::isfinite(*m)) return fail(c, LBM_ENONFINITE, "monitor found a non-finite mass");
+  return LBM_OK;
+}
+
+int lbm_get_f(lbm_ctx* c, double* f) {
+  if (!c || !f) return LBM_EINVAL;
+  DevTmp tmp;
+  HIPCHK(c, hipMalloc(&tmp.p, c->N * sizeof(double)));
+  const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
+  for (int a = 0; a < c->q; ++a) {
+    HIPCHK(c, launch_get_pop(c->q, c->spec.storage, phase, a, args_ptr(*c), (double*)tmp.p,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(f + (size_t)a * c->N, tmp.p, c->N * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_set_f(lbm_ctx* c, const double* f) {
+  if (!c || !f) return LBM_EINVAL;
+  DevTmp tmp;
+  HIPCHK(c, hipMalloc(&tmp.p, c->N * sizeof(double)));
+  // the natural layout is written: AA parity restarts at 0
+  c->phase = 0;
+  for (int a = 0; a < c->q; ++a) {
+    HIPCHK(c, hipMemcpyAsync(tmp.p, f + (size_t)a * c->N, c->N * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_set_pop(c->q, c->spec.storage, a, args_ptr(*c), (const double*)tmp.p,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  c->snap_valid = false;
+  return LBM_OK;
+}
+
+int lbm_init_fields(lbm_ctx* c, const double* p, const double* u) {
+  if (!c) return LBM_EINVAL;
+  DevTmp tp, tu;
+  if (p) {
+    HIPCHK(c, hipMalloc(&tp.p, c->N * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(tp.p, p, c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  if (u) {
+    HIPCHK(c, hipMalloc(&tu.p, 3 * c->N * sizeof(double)));
+    HIPCHK(c, hipMemcpyAsync(tu.p, u, 3 * c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  c->phase = 0;
+  set_force(*c, c->t);
+  HIPCHK(c, launch_init_eq(c->q, c->spec.storage, args_ptr(*c), (const double*)tp.p,
+                           (const double*)tu.p, c->spec.p0, c->spec.u0, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->snap_valid = false;
+  return LBM_OK;
+}
+
+long long lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+int lbm_set_time(lbm_ctx* c, long long t) {
+  if (!c || t < 0) return LBM_EINVAL;
+  c->t = t;
+  c->snap_valid = false;
+  return LBM_OK;
+}
+
+int lbm_info(const lbm_ctx* c, lbm_info_t* info) {
+  if (!c || !info) return LBM_EINVAL;
+  info->q = c->q;
+  info->nx = c->nx;
+  info->ny = c->ny;
+  info->nz = c->nz;
+  info->storage = c->spec.storage;
+  info->pattern = c->spec.pattern;
+  info->t = c->t;
+  info->nodes = c->N;
+  info->population_bytes = population_bytes(c->q, c->N, c->spec.storage);
+  info->footprint_bytes = c->footprint;
+  info->bytes_per_value = bytes_of(c->spec.storage);
+  return LBM_OK;
+}
+
+int lbm_sync(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+const char* lbm_status_string(int s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of device memory";
+    case LBM_EDEVICE: return "device error";
+    case LBM_ENONFINITE: return "non-finite value";
+    case LBM_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+int lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  if (c->batch) (void)lbm_batch_remove((lbm_batch*)c->batch, c);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->own_buf && c->buf) (void)hipFree(c->buf);
+  if (c->mon_buf) (void)hipFree(c->mon_buf);
+  delete c;
+  return LBM_OK;
+}
+
+int lbm_copy_probe(void* dst, const void* src, size_t bytes, int reps, void* stream) {
+  if (!dst || !src || bytes % 16 || reps < 0) return LBM_EINVAL;
+  for (int i = 0; i < reps; ++i)
+    if (launch_copy_probe(dst, src, bytes, (hipStream_t)stream) != hipSuccess) return LBM_EDEVICE;
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+// ============================ batches =======================================
+namespace {
+struct Member {
+  lbm_ctx* ctx;
+  long long remaining;
+  int tx, ty;  // 0: automatic
+};
+}  // namespace
+
+struct lbm_batch {
+  hipStream_t stream = nullptr;
+  std::vector<Member> members;
+  std::string err;
+  // device staging (grown on demand)
+  BatchMember* d_members = nullptr;
+  size_t d_members_cap = 0;
+  float* d_ftab = nullptr;
+  size_t d_ftab_cap = 0;
+  // pinned host staging + the event that says it may be reused
+  BatchMember* h_members = nullptr;
+  size_t h_members_cap = 0;
+  float* h_ftab = nullptr;
+  size_t h_ftab_cap = 0;
+  hipEvent_t staged = nullptr;
+  // monitor staging
+  char* d_mon = nullptr;
+  size_t d_mon_cap = 0;
+};
+
+namespace {
+int bfail(lbm_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+#define BHIP(b, call)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) return bfail(b, LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+int grow_dev(lbm_batch* b, T*& p, size_t& cap, size_t n) {
+  if (n <= cap) return LBM_OK;
+  if (p) BHIP(b, hipFree(p));
+  p = nullptr;
+  size_t c = std::max<size_t>(n, cap * 2);
+  BHIP(b, hipMalloc((void**)&p, c * sizeof(T)));
+  cap = c;
+  return LBM_OK;
+}
+template <typename T>
+int grow_host(lbm_batch* b, T*& p, size_t& cap, size_t n) {
+  if (n <= cap) return LBM_OK;
+  if (p) BHIP(b, hipHostFree(p));
+  p = nullptr;
+  size_t c = std::max<size_t>(n, cap * 2);
+  BHIP(b, hipHostMalloc((void**)&p, c * sizeof(T), hipHostMallocDefault));
+  cap = c;
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(lbm_batch** out, void* stream) {
+  if (!out) return LBM_EINVAL;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ENOMEM;
+  b->stream = (hipStream_t)stream;
+  if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    return LBM_EDEVICE;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_add(lbm_batch* b, lbm_ctx* c, long long budget) {
+  if (!b || !c || budget < 0) return LBM_EINVAL;
+  if (c->batch) return bfail(b, LBM_EINVAL, "context already belongs to a batch");
+  if (c->spec.pattern != LBM_AA) return bfail(b, LBM_EINVAL, "batched members must use LBM_AA");
+  if (c->spec.storage == LBM_F64)
+    return bfail(b, LBM_EINVAL, "batched members must store LBM_F32 or LBM_F16DEV");
+  if (c->stream != b->stream) return bfail(b, LBM_EINVAL, "member stream differs from batch stream");
+  b->members.push_back(Member{c, budget, 0, 0});
+  c->batch = b;
+  return LBM_OK;
+}
+
+int lbm_batch_remove(lbm_batch* b, lbm_ctx* c) {
+  if (!b || !c) return LBM_EINVAL;
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (b->members[i].ctx == c) {
+      b->members.erase(b->members.begin() + i);
+      c->batch = nullptr;
+      return LBM_OK;
+    }
+  return bfail(b, LBM_EINVAL, "not a member");
+}
+
+int lbm_batch_set_tile(lbm_batch* b, lbm_ctx* c, int tx, int ty) {
+  if (!b || !c) return LBM_EINVAL;
+  if (tx < 0 || ty < 0 || (long long)tx * ty > 256 || ((tx == 0) != (ty == 0)))
+    return bfail(b, LBM_EINVAL, "tile must satisfy 1 <= tx*ty <= 256 (or 0,0)");
+  for (auto& m : b->members)
+    if (m.ctx == c) {
+      m.tx = tx;
+      m.ty = ty;
+      return LBM_OK;
+    }
+  return bfail(b, LBM_EINVAL, "not a member");
+}
+
+long long lbm_batch_remaining(const lbm_batch* b, const lbm_ctx* c) {
+  if (!b || !c) return -1;
+  for (const auto& m : b->members)
+    if (m.ctx == c) return m.remaining;
+  return -1;
+}
+
+int lbm_batch_size(const lbm_batch* b) { return b ? (int)b->members.size() : 0; }
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int lbm_batch_step(lbm_batch* b, long long n) {
+  if (!b || n < 0) return LBM_EINVAL;
+  if (n == 0 || b->members.empty()) return LBM_OK;
+  if (n > (1LL << 30)) return bfail(b, LBM_EINVAL, "n too large for one call");
+  // active members and their step counts for this call
+  std::vector<int> act;
+  long long nmax = 0;
+  size_t ftab_rows = 0;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    const long long k = std::min(n, b->members[i].remaining);
+    if (k <= 0) continue;
+    act.push_back((int)i);
+    nmax = std::max(nmax, k);
+    if (b->members[i].ctx->forced) ftab_rows += (size_t)k;
+  }
+  if (act.empty()) return LBM_OK;
+  const int nm = (int)act.size();
+  // the pinned staging may still be read by the previous upload
+  BHIP(b, hipEventSynchronize(b->staged));
+  int rc = grow_host(b, b->h_members, b->h_members_cap, (size_t)nm);
+  if (!rc) rc = grow_dev(b, b->d_members, b->d_members_cap, (size_t)nm);
+  if (!rc) rc = grow_host(b, b->h_ftab, b->h_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
+  if (!rc) rc = grow_dev(b, b->d_ftab, b->d_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
+  if (rc) return rc;
+  long long tiles = 0;
+  size_t frow = 0;
+  for (int j = 0; j < nm; ++j) {
+    Member& m = b->members[act[j]];
+    lbm_ctx* c = m.ctx;
+    BatchMember& bm = b->h_members[j];
+    std::memset(&bm, 0, sizeof(bm));
+    int tx = m.tx, ty = m.ty;
+    if (tx == 0) pick_tile(c->nx, c->ny, tx, ty);
+    const int save_tx = c->tx, save_ty = c->ty;
+    c->tx = tx;
+    c->ty = ty;
+    fill_args<float>(*c, bm.a);
+    c->tx = save_tx;
+    c->ty = save_ty;
+    bm.q = c->q;
+    bm.storage = c->spec.storage == LBM_F32 ? ST_F32 : ST_F16;
+    bm.phase0 = c->phase;
+    const long long k = std::min(n, m.remaining);
+    bm.steps = (int)k;
+    bm.tile_begin = tiles;
+    bm.ntiles = (long long)bm.a.tiles_x * bm.a.tiles_y * c->nz;
+    tiles += bm.ntiles;
+    bm.forced = c->forced ? 1 : 0;
+    bm.ftab_off = 3LL * (long long)frow;
+    if (c->forced) {
+      for (long long s = 0; s < k; ++s) {
+        double F[3];
+        force_at(c->spec, c->t + s, F);
+        for (int d = 0; d < 3; ++d) b->h_ftab[3 * (frow + s) + d] = (float)F[d];
+      }
+      frow += (size_t)k;
+    }
+  }
+  if (tiles >= (1LL << 31)) return bfail(b, LBM_EINVAL, "too many tiles in one batch");
+  BHIP(b, hipMemcpyAsync(b->d_members, b->h_members, nm * sizeof(BatchMember),
+                         hipMemcpyHostToDevice, b->stream));
+  if (frow)
+    BHIP(b, hipMemcpyAsync(b->d_ftab, b->h_ftab, 3 * frow * sizeof(float), hipMemcpyHostToDevice,
+                           b->stream));
+  BHIP(b, hipEventRecord(b->staged, b->stream));
+  for (long long s = 0; s < nmax; ++s)
+    BHIP(b, launch_batch_step(b->d_members, nm, tiles, b->d_ftab, (int)s, b->stream));
+  for (int j = 0; j < nm; ++j) {
+    Member& m = b->members[act[j]];
+    const long long k = std::min(n, m.remaining);
+    m.ctx->t += k;
+    m.ctx->phase = (int)((m.ctx->phase + k) & 1);
+    m.remaining -= k;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_monitor(lbm_batch* b) {
+  if (!b) return LBM_EINVAL;
+  const int nm = (int)b->members.size();
+  if (nm == 0) return LBM_OK;
+  for (auto& m : b->members) {
+    int rc = ensure_monitor(m.ctx);
+    if (rc) return bfail(b, rc, m.ctx->err);
+  }
+  // layout of the staging block: members | snaps | pofs | bbeg | pcount |
+  // phases | partials | out
+  std::vector<BatchMember> hm(nm);
+  std::vector<void*> snaps(nm);
+  std::vector<long long> pofs(nm), bbeg(nm), pcount(nm);
+  std::vector<int> phases(nm);
+  long long blocks = 0;
+  for (int j = 0; j < nm; ++j) {
+    lbm_ctx* c = b->members[j].ctx;
+    std::memset(&hm[j], 0, sizeof(BatchMember));
+    fill_args<float>(*c, hm[j].a);
+    double F[3];
+    force_at(c->spec, c->t, F);
+    for (int d = 0; d < 3; ++d) hm[j].a.F[d] = (float)F[d];
+    hm[j].q = c->q;
+    hm[j].storage = c->spec.storage == LBM_F32 ? ST_F32 : ST_F16;
+    snaps[j] = c->snap;
+    long long nb = ((long long)c->N + 255) / 256;
+    nb = std::max(1LL, std::min(nb, 256LL));
+    bbeg[j] = blocks;
+    pofs[j] = blocks;
+    pcount[j] = nb;
+    phases[j] = c->phase;
+    blocks += nb;
+  }
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    size_t o = align_up(off);
+    off = o + bytes;
+    return o;
+  };
+  const size_t o_m = place(nm * sizeof(BatchMember));
+  const size_t o_s = place(nm * sizeof(void*));
+  const size_t o_p = place(nm * sizeof(long long));
+  const size_t o_b = place(nm * sizeof(long long));
+  const size_t o_c = place(nm * sizeof(long long));
+  const size_t o_h = place(nm * sizeof(int));
+  const size_t o_part = place(3 * blocks * sizeof(double));
+  const size_t o_out = place(3 * nm * sizeof(double));
+  int rc = grow_dev(b, b->d_mon, b->d_mon_cap, off);
+  if (rc) return rc;
+  char* d = b->d_mon;
+  BHIP(b, hipMemcpyAsync(d + o_m, hm.data(), nm * sizeof(BatchMember), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(d + o_s, snaps.data(), nm * sizeof(void*), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(d + o_p, pofs.data(), nm * sizeof(long long), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(d + o_b, bbeg.data(), nm * sizeof(long long), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(d + o_c, pcount.data(), nm * sizeof(long long), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(d + o_h, phases.data(), nm * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, launch_batch_monitor((const BatchMember*)(d + o_m), nm, (void* const*)(d + o_s),
+                               (double*)(d + o_part), (const long long*)(d + o_p), blocks,
+                               (const long long*)(d + o_b), (const int*)(d + o_h), b->stream));
+  BHIP(b, launch_batch_reduce((const double*)(d + o_part), (const long long*)(d + o_p),
+                              (const long long*)(d + o_c), nm, (double*)(d + o_out), b->stream));
+  std::vector<double> res(3 * nm);
+  BHIP(b, hipMemcpyAsync(res.data(), d + o_out, 3 * nm * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  for (int j = 0; j < nm; ++j) {
+    lbm_ctx* c = b->members[j].ctx;
+    c->mon[0] = res[3 * j];
+    c->mon[1] = res[3 * j + 1];
+    c->mon[2] = res[3 * j + 2];
+    c->mon_lag = c->snap_valid ? c->t - c->t_snap : 0;
+    c->snap_valid = true;
+    c->t_snap = c->t;
+    c->mon_ran = true;
+    c->mon_pending = false;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& m : b->members) m.ctx->batch = nullptr;
+  if (b->d_members) (void)hipFree(b->d_members);
+  if (b->d_ftab) (void)hipFree(b->d_ftab);
+  if (b->d_mon) (void)hipFree(b->d_mon);
+  if (b->h_members) (void)hipHostFree(b->h_members);
+  if (b->h_ftab) (void)hipHostFree(b->h_ftab);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  delete b;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,51 @@
+"""Relaxation vectors and flow set-ups in lattice units (c = dx = dt = 1).
+
+Rates follow Sec. 4 of arXiv 1503.03337: s_c = 1.0, s_e = 1.19, s_q = 1.2,
+s_t = 0.98, s_nu = 1/tau with nu = (1/s_nu - 1/2)/3 (Eq. (vis)).  The
+18-velocity model (Appendix B) also needs s_pi, which the paper does not
+give; 1.4 is used.
+"""
+import numpy as np
+
+S_C, S_E, S_Q, S_T, S_PI = 1.0, 1.19, 1.2, 0.98, 1.4
+
+# u_max of steady flow in a square duct of half-width a under body force g:
+# u_max = DUCT_UMAX_COEFF * g a^2 / nu (Sec. 4.1 series at the centre).
+DUCT_UMAX_COEFF = 0.2946854131260552
+
+
+def s_nu(nu):
+    return 1.0 / (3.0 * nu + 0.5)
+
+
+def s_vec(q, nu=None, sn=None, s_e=S_E, s_q=S_Q, s_t=S_T, s_pi=S_PI, s_c=S_C):
+    """Relaxation rates in the moment order of Eq. (moment) (q = 14) or
+    Eq. (d3q18moment) (q = 18)."""
+    if sn is None:
+        sn = s_nu(nu)
+    if q == 14:
+        return np.array([s_c, s_e, s_c, s_q, s_c, s_q, s_c, s_q, sn, sn, sn, sn, sn, s_t])
+    if q == 18:
+        return np.array([s_c, s_e, s_c, s_q, s_c, s_q, s_c, s_q, sn, s_pi, sn, s_pi, sn, sn, sn,
+                         s_t, s_t, s_t])
+    raise ValueError("q must be 14 or 18")
+
+
+DUCT_FACES = ("periodic", "periodic", "wall", "wall", "wall", "wall")
+CAVITY_FACES = ("wall",) * 6
+
+
+def duct(q, edge, length, nu, umax=0.05):
+    """Square duct: x periodic (length), y and z half-way walls (edge), body
+    force along x sized for centre-line speed umax."""
+    a = edge / 2.0
+    g = umax * nu / (DUCT_UMAX_COEFF * a * a)
+    return {"model": q, "nx": length, "ny": edge, "nz": edge, "s_vec": s_vec(q, nu),
+            "faces": DUCT_FACES, "F0": (g, 0.0, 0.0)}
+
+
+def cavity(q, edge, Re, lid=0.1):
+    """Cubic lid-driven cavity: six walls, the +z lid moving along +x."""
+    nu = lid * edge / Re
+    return {"model": q, "nx": edge, "ny": edge, "nz": edge, "s_vec": s_vec(q, nu),
+            "faces": CAVITY_FACES, "wall_u": {"+z": (lid, 0.0, 0.0)}}

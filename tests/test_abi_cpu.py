@@ -1,0 +1,90 @@
+"""CPU-side checks of the C ABI: the built library loads and exports every
+function include/lbm.h declares; the calls that touch no device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_core_entry_points():
+    names = declared_functions()
+    for core in ("lbm_create", "lbm_step", "lbm_macros", "lbm_residual", "lbm_mass",
+                 "lbm_get_f", "lbm_set_f", "lbm_destroy", "lbm_batch_step"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1503_03337_amd import lbm
+    L = lbm.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    # and the binding wraps each of them
+    src = open(os.path.join(ROOT, "paper_1503_03337_amd", "lbm.py")).read()
+    for name in declared_functions():
+        assert '"%s"' % name in src, name
+
+
+def test_footprint_without_device():
+    from paper_1503_03337_amd import lbm
+    n = 128
+    assert lbm.footprint_bytes(18, n, n, n, storage="f32", pattern="aa") == 18 * n ** 3 * 4
+    assert lbm.footprint_bytes(18, n, n, n, storage="f32", pattern="ab") == 2 * 18 * n ** 3 * 4
+    assert lbm.footprint_bytes(14, n, n, n, storage="f16dev", pattern="aa") == 14 * n ** 3 * 2
+    assert lbm.footprint_bytes(14, 16, 16, 32, storage="f64", pattern="ab") == 2 * 14 * 8192 * 8
+    with_mon = lbm.footprint_bytes(18, n, n, n, storage="f32", pattern="aa", monitor_every=10)
+    assert with_mon >= 18 * n ** 3 * 4 + 3 * n ** 3 * 4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(model=15), dict(nx=0), dict(faces=("periodic", "wall") + ("wall",) * 4),
+    dict(wall_u={"+z": (0.3, 0, 0)}), dict(storage=7), dict(pattern=5),
+    dict(storage="f16dev", f16_scale_log2=30), dict(monitor_every=-1),
+])
+def test_footprint_rejects_invalid(bad):
+    from paper_1503_03337_amd import lbm
+    args = dict(model=18, nx=8, ny=8, nz=8)
+    args.update({k: v for k, v in bad.items() if k in args})
+    kw = {k: v for k, v in bad.items() if k not in ("model", "nx", "ny", "nz")}
+    assert lbm.footprint_bytes(args["model"], args["nx"], args["ny"], args["nz"], **kw) == 0
+
+
+def test_status_strings():
+    from paper_1503_03337_amd import lbm
+    L = lbm.lib()
+    assert L.lbm_status_string(0) == b"ok"
+    assert L.lbm_status_string(-4) == b"non-finite value"
+
+
+def test_create_rejects_bad_rates_without_device():
+    """Validation happens before any device call."""
+    import numpy as np
+    from paper_1503_03337_amd import lbm
+    L = lbm.lib()
+    sp = lbm.make_spec()
+    h = C.c_void_p()
+    s = np.full(18, 2.0)
+    assert L.lbm_create(C.byref(h), 18, 8, 8, 8, s.ctypes.data_as(C.POINTER(C.c_double)),
+                        C.byref(sp)) == -1
+    s = np.full(18, 1.0)
+    assert L.lbm_create(C.byref(h), 16, 8, 8, 8, s.ctypes.data_as(C.POINTER(C.c_double)),
+                        C.byref(sp)) == -1
+
+
+def test_params_match_paper_rates():
+    from paper_1503_03337_amd import params
+    s = params.s_vec(14, nu=0.1)
+    assert s[1] == 1.19 and s[3] == 1.2 and s[13] == 0.98 and s[0] == 1.0
+    assert abs(s[8] - 1.25) < 1e-15
+    from oracle import analytic
+    assert abs(params.DUCT_UMAX_COEFF - analytic.duct_steady_umax_coeff()) < 1e-14

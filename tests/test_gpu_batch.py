@@ -1,0 +1,171 @@
+"""Batched execution (one launch per time step over many lattices) through
+the C ABI: alone == in the mix (bit-exact), batch == single-lattice kernel,
+batch == oracle within the FP32 tolerance, step budgets, continuous
+admission/retirement, tile-shape invariance, batched monitors."""
+import numpy as np
+import pytest
+
+from helpers import svec
+from oracle import runner as R
+from paper_1503_03337_amd import inputs
+from paper_1503_03337_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [
+    # q, dims, storage, faces, wall_u, F0, FA, FT
+    (14, (24, 17, 13), "f32", ("periodic", "periodic", "wall", "wall", "wall", "wall"),
+     None, (2e-5, 0, 0), (0, 0, 0), 0.0),
+    (18, (19, 23, 11), "f16dev", ("wall",) * 6, {"+z": (0.1, 0, 0)}, (0, 0, 0), (0, 0, 0), 0.0),
+    (18, (40, 9, 9), "f32", ("periodic", "periodic", "wall", "wall", "wall", "wall"),
+     {"-y": (0.01, 0, 0)}, (1e-5, 0, 0), (2e-5, 0, 0), 9.0),
+    (14, (13, 29, 7), "f16dev", ("wall",) * 6, {"+z": (0.05, 0.02, 0)}, (0, 0, 0), (0, 0, 0),
+     0.0),
+    (18, (300, 4, 3), "f32", ("periodic",) * 6, None, (1e-5, 1e-5, 0), (0, 0, 0), 0.0),
+]
+
+
+def rates(q, k):
+    return svec(q, 1.3 + 0.1 * k) + np.linspace(-0.02, 0.02, q)
+
+
+def build(k, seed):
+    q, dims, storage, faces, wall_u, F0, FA, FT = MEMBERS[k]
+    lat = lbm.Lattice(q, *dims, rates(q, k), faces=faces, wall_u=wall_u, F0=F0, FA=FA, FT=FT,
+                      storage=storage, pattern="aa")
+    lat.set_f(inputs.random_populations(q, *dims, seed=seed))
+    return lat
+
+
+def run_alone(k, nsteps, seed, via_batch=True):
+    lat = build(k, seed)
+    if via_batch:
+        b = lbm.Batch(lat.stream)
+        b.add(lat, nsteps)
+        b.step(nsteps)
+        b.close()
+    else:
+        lat.step(nsteps)
+    f = lat.get_f()
+    lat.close()
+    return f
+
+
+def test_alone_equals_mix_bit_exact():
+    budgets = [7, 5, 9, 6, 8]
+    alone = [run_alone(k, budgets[k], 100 + k) for k in range(len(MEMBERS))]
+    lats = [build(k, 100 + k) for k in range(len(MEMBERS))]
+    b = lbm.Batch(lats[0].stream)
+    for k, lat in enumerate(lats):
+        b.add(lat, budgets[k])
+    b.step(4)
+    b.step(10)  # members stop at their own budgets
+    for k, lat in enumerate(lats):
+        assert b.remaining(lat) == 0
+        assert lat.time == budgets[k]
+        assert np.array_equal(lat.get_f(), alone[k]), "member %d" % k
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
+def test_batch_equals_single_kernel():
+    for k in range(len(MEMBERS)):
+        a = run_alone(k, 6, 200 + k, via_batch=True)
+        s = run_alone(k, 6, 200 + k, via_batch=False)
+        assert np.linalg.norm(a - s) <= 1e-6 * np.linalg.norm(s), "member %d" % k
+
+
+def test_batch_matches_oracle():
+    for k in range(len(MEMBERS)):
+        q, dims, storage, faces, wall_u, F0, FA, FT = MEMBERS[k]
+        lat = build(k, 300 + k)
+        f0 = lat.get_f()
+        b = lbm.Batch(lat.stream)
+        b.add(lat, 5)
+        b.step(5)
+        pr = R.problem(q, *dims, rates(q, k), faces=faces, wall_u=wall_u, F0=F0, FA=FA, FT=FT)
+        ref = R.run(pr, f0, 0, 5)
+        _, u = lat.macros()
+        _, ur = R.macros(pr, ref, 5)
+        tol = 1e-5 if storage == "f32" else 3e-3
+        assert np.linalg.norm(u - ur) <= tol * np.linalg.norm(ur), "member %d" % k
+        b.close()
+        lat.close()
+
+
+def test_continuous_admission_and_retirement():
+    """Members join and leave between calls; everyone's result equals its
+    alone run."""
+    alone = {k: run_alone(k, 12, 400 + k) for k in (0, 1, 2)}
+    l0, l1, l2 = (build(k, 400 + k) for k in (0, 1, 2))
+    b = lbm.Batch(l0.stream)
+    b.add(l0, 12)
+    b.step(3)
+    b.add(l1, 12)   # arrives while l0 runs
+    b.step(5)
+    b.add(l2, 12)
+    b.step(4)       # l0 done (12)
+    assert b.remaining(l0) == 0
+    b.remove(l0)
+    assert len(b) == 2
+    b.step(100)     # l1 (9 left) and l2 (8 left) finish
+    for lat, k in ((l0, 0), (l1, 1), (l2, 2)):
+        assert lat.time == 12
+        assert np.array_equal(lat.get_f(), alone[k]), "member %d" % k
+    b.close()
+    for lat in (l0, l1, l2):
+        lat.close()
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (64, 4), (32, 8), (7, 9), (1, 1)])
+def test_tile_shape_does_not_change_results(tile):
+    ref = run_alone(2, 5, 500)
+    lat = build(2, 500)
+    b = lbm.Batch(lat.stream)
+    b.add(lat, 5)
+    b.set_tile(lat, *tile)
+    b.step(5)
+    assert np.array_equal(lat.get_f(), ref)
+    b.close()
+    lat.close()
+
+
+def test_batch_monitor_matches_single_monitor():
+    lats = [build(k, 600 + k) for k in range(3)]
+    b = lbm.Batch(lats[0].stream)
+    for lat in lats:
+        b.add(lat, 50)
+    b.step(10)
+    b.monitor()
+    b.step(10)
+    b.monitor()
+    for k, lat in enumerate(lats):
+        r, m = lat.residual(), lat.mass()
+        # same state through the single-lattice monitor
+        ref = build(k, 600 + k)
+        ref.step(10)
+        ref.monitor()
+        ref.step(10)
+        ref.monitor()
+        rr, mr = ref.residual(), ref.mass()
+        ref.close()
+        assert abs(r - rr) <= 1e-6 * abs(rr), (k, r, rr)
+        assert abs(m - mr) <= 1e-9 * max(1.0, abs(mr)), (k, m, mr)
+    b.close()
+    for lat in lats:
+        lat.close()
+
+
+def test_batch_rejects_unsupported_members():
+    q = 18
+    lat = lbm.Lattice(q, 8, 8, 8, svec(q, 1.2), storage="f64")
+    b = lbm.Batch(lat.stream)
+    with pytest.raises(lbm.LbmError):
+        b.add(lat, 10)
+    lat2 = lbm.Lattice(q, 8, 8, 8, svec(q, 1.2), storage="f32", pattern="ab")
+    with pytest.raises(lbm.LbmError):
+        b.add(lat2, 10)
+    b.close()
+    lat.close()
+    lat2.close()

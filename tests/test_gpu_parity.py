@@ -1,0 +1,310 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle on the same seeded
+inputs.
+
+Tolerances (derived in the design doc):
+  FP64 storage: populations element-wise within 1e-13 of max|f|;
+                p and u relative L2 (GRE form, Eq. (ed)) <= 1e-12.
+  FP32 storage: p and u relative L2 <= 1e-5 (FP32 unit roundoff 6e-8 per
+                operation, a few hundred operations per node-step).
+  FP16-deviation storage: one step element-wise within one FP16 rounding
+                (2^-11 relative) plus the FP32 arithmetic; after k steps
+                populations within 2 sqrt(k) 2^-11 relative L2, velocity
+                within k * 10 * 2^-11 max|f| (one rounding per population
+                and step, at most 10 populations per component).
+Bit-exact: zero rates (pure streaming permutation), AA against AB, and
+checkpoint/restore.
+"""
+import numpy as np
+import pytest
+
+from helpers import svec
+from oracle import runner as R
+from paper_1503_03337_amd import inputs
+from paper_1503_03337_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+FACESETS = {
+    "periodic": ("periodic",) * 6,
+    "duct": ("periodic", "periodic", "wall", "wall", "wall", "wall"),
+    "cavity": ("wall",) * 6,
+    "xwalls": ("wall", "wall", "periodic", "periodic", "periodic", "periodic"),
+}
+SETUPS = {
+    # name: (faces, wall_u, F0, FA, FT)
+    "periodic_force": ("periodic", None, (2e-5, -1e-5, 3e-5), (0, 0, 0), 0.0),
+    "duct_pulsatile": ("duct", {"+y": (0.02, 0.0, 0.01)}, (1e-5, 0, 0), (3e-5, 0, 0), 7.0),
+    "cavity_lid": ("cavity", {"+z": (0.1, 0.0, 0.0), "-x": (0.0, 0.03, 0.0)}, (0, 0, 0),
+                   (0, 0, 0), 0.0),
+    "xwalls_force": ("xwalls", {"-x": (0.0, 0.05, 0.0)}, (0, 2e-5, 0), (0, 0, 0), 0.0),
+}
+DIMS = [(37, 19, 11), (300, 3, 4)]
+
+
+def rates(q, seed=0):
+    s = svec(q, 1.45).astype(float)
+    return s + np.linspace(-0.03, 0.03, q)  # all rates distinct
+
+
+def make_pair(q, dims, setup, storage, pattern, seed=0, s=None):
+    faces, wall_u, F0, FA, FT = SETUPS[setup]
+    faces = FACESETS[faces]
+    s = rates(q) if s is None else s
+    lat = lbm.Lattice(q, *dims, s, faces=faces, wall_u=wall_u, F0=F0, FA=FA, FT=FT,
+                      storage=storage, pattern=pattern)
+    pr = R.problem(q, *dims, s, faces=faces, wall_u=wall_u, F0=F0, FA=FA, FT=FT)
+    f0 = inputs.random_populations(q, *dims, seed=seed)
+    lat.set_f(f0)
+    f0q = lat.get_f()  # the initial state as the storage type holds it
+    return lat, pr, f0q
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("setup", sorted(SETUPS))
+@pytest.mark.parametrize("dims", DIMS, ids=lambda d: "x".join(map(str, d)))
+def test_fp64_matches_oracle(q, pattern, setup, dims):
+    print("case q=%d %s %s %s" % (q, pattern, setup, dims), flush=True)
+    lat, pr, f0 = make_pair(q, dims, setup, "f64", pattern)
+    lat.step(2)  # AA: ends on the natural layout
+    got = lat.get_f()
+    ref = R.run(pr, f0, 0, 2)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    lat.step(1)  # AA: ends on the swapped layout (get_f gathers)
+    got = lat.get_f()
+    ref = R.run(pr, ref, 2, 1)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    p, u = lat.macros()
+    pr_, ur_ = R.macros(pr, ref, 3)
+    assert rel_l2(u, ur_) <= 1e-12
+    assert rel_l2(p, pr_) <= 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("setup", sorted(SETUPS))
+def test_fp32_matches_oracle(q, pattern, setup):
+    dims = DIMS[0]
+    print("case q=%d %s %s" % (q, pattern, setup), flush=True)
+    lat, pr, f0 = make_pair(q, dims, setup, "f32", pattern, seed=1)
+    lat.step(5)
+    ref = R.run(pr, f0, 0, 5)
+    p, u = lat.macros()
+    pr_, ur_ = R.macros(pr, ref, 5)
+    assert rel_l2(u, ur_) <= 1e-5
+    assert rel_l2(p, pr_) <= 1e-5
+    assert rel_l2(lat.get_f(), ref) <= 1e-6
+    lat.close()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("setup", ("cavity_lid", "duct_pulsatile"))
+def test_fp16dev_matches_oracle(q, pattern, setup):
+    dims = DIMS[0]
+    print("case q=%d %s %s" % (q, pattern, setup), flush=True)
+    lat, pr, f0 = make_pair(q, dims, setup, "f16dev", pattern, seed=2)
+    lat.step(1)
+    got = lat.get_f()
+    ref = R.run(pr, f0, 0, 1)
+    # one FP16 rounding of an FP32 result (plus FP32 arithmetic)
+    bound = 2.0 ** -11 * np.abs(ref) + 1e-6 * np.max(np.abs(ref))
+    assert np.all(np.abs(got - ref) <= bound)
+    # k steps: every stored population carries at most one FP16 rounding
+    # (2^-11 of max|f|) per step, and each velocity component sums at most
+    # 10 populations; the populations' relative L2 grows like sqrt(k).
+    k = 4
+    lat.step(k - 1)
+    ref = R.run(pr, ref, 1, k - 1)
+    got = lat.get_f()
+    assert rel_l2(got, ref) <= 2.0 * np.sqrt(k) * 2.0 ** -11
+    p, u = lat.macros()
+    pr_, ur_ = R.macros(pr, ref, k)
+    fmax = np.max(np.abs(ref))
+    assert np.max(np.abs(u - ur_)) <= k * 10 * 2.0 ** -11 * fmax
+    assert np.max(np.abs(p - pr_)) <= k * q * 2.0 ** -11 * fmax
+    lat.close()
+
+
+def pull_permutation(q, dims, faces, f):
+    """Pure streaming written in pull form (test-side, independent)."""
+    c, _, opp, _, _, _ = R.lattice(q)
+    nx, ny, nz = dims
+    out = np.empty_like(f)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for a in range(q):
+        src = [x - c[a, 0], y - c[a, 1], z - c[a, 2]]
+        wall = np.zeros(x.shape, bool)
+        for d, n in enumerate(dims):
+            if faces[2 * d] == "periodic":
+                src[d] = src[d] % n
+            else:
+                wall |= (src[d] < 0) | (src[d] >= n)
+                src[d] = np.clip(src[d], 0, n - 1)
+        moved = f[a][src[2], src[1], src[0]]
+        out[a] = np.where(wall, f[opp[a]], moved)
+    return out
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("storage", ("f64", "f32", "f16dev"))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("faces", sorted(FACESETS))
+def test_zero_rates_bit_exact_permutation(q, storage, pattern, faces):
+    dims = (37, 19, 11)
+    fs = FACESETS[faces]
+    lat = lbm.Lattice(q, *dims, np.zeros(q), faces=fs, storage=storage, pattern=pattern)
+    lat.set_f(inputs.random_populations(q, *dims, seed=3))
+    f = lat.get_f()
+    for k in range(3):
+        lat.step(1)
+        f = pull_permutation(q, dims, fs, f)
+        assert np.array_equal(lat.get_f(), f), "step %d" % (k + 1)
+    lat.close()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("storage", ("f64", "f32", "f16dev"))
+@pytest.mark.parametrize("setup", sorted(SETUPS))
+def test_aa_equals_ab_bit_exact(q, storage, setup):
+    out = {}
+    for pattern in ("ab", "aa"):
+        lat, _, _ = make_pair(q, DIMS[0], setup, storage, pattern, seed=4)
+        lat.step(5)
+        out[pattern] = (lat.get_f(), lat.macros())
+        lat.close()
+    assert np.array_equal(out["ab"][0], out["aa"][0])
+    assert np.array_equal(out["ab"][1][0], out["aa"][1][0])
+    assert np.array_equal(out["ab"][1][1], out["aa"][1][1])
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("storage,pattern,split", [
+    ("f64", "ab", 3), ("f32", "aa", 3), ("f32", "aa", 4), ("f16dev", "aa", 4), ("f32", "ab", 2)])
+def test_checkpoint_restore_bit_exact(q, storage, pattern, split):
+    setup = "duct_pulsatile"
+    ref, _, f0 = make_pair(q, DIMS[0], setup, storage, pattern, seed=5)
+    ref.step(8)
+    want = ref.get_f()
+    a, _, _ = make_pair(q, DIMS[0], setup, storage, pattern, seed=5)
+    a.step(split)
+    ck, t = a.get_f(), a.time
+    a.close()
+    b, _, _ = make_pair(q, DIMS[0], setup, storage, pattern, seed=6)
+    b.set_f(ck)
+    b.set_time(t)
+    b.step(8 - split)
+    assert np.array_equal(b.get_f(), want)
+    ref.close()
+    b.close()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("storage", ("f64", "f32"))
+def test_init_fields_match_oracle(q, storage):
+    dims = (21, 13, 9)
+    faces, wall_u, F0, FA, FT = SETUPS["duct_pulsatile"]
+    p, u = inputs.random_fields(*dims, seed=7)
+    lat = lbm.Lattice(q, *dims, rates(q), faces=FACESETS[faces], F0=F0, FA=FA, FT=FT,
+                      storage=storage)
+    lat.init_fields(p, u)
+    pr = R.problem(q, *dims, rates(q), faces=FACESETS[faces], F0=F0, FA=FA, FT=FT)
+    ref = R.init_eq(pr, 0, p=p, u=u)
+    got = lat.get_f()
+    tol = 1e-15 if storage == "f64" else 1e-7  # a few ulps of differing operation order
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+    # the recovered velocity is the one put in (Eq. (hgl))
+    _, ug = lat.macros()
+    assert np.max(np.abs(ug - u)) <= (1e-16 if storage == "f64" else 1e-8)
+    lat.close()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+def test_monitor_mass_and_residual(q, pattern):
+    dims = DIMS[0]
+    setup = "cavity_lid"
+    faces, wall_u, F0, FA, FT = SETUPS[setup]
+    lat = lbm.Lattice(q, *dims, rates(q), faces=FACESETS[faces], wall_u=wall_u,
+                      storage="f64", pattern=pattern, monitor_every=3)
+    pr = R.problem(q, *dims, rates(q), faces=FACESETS[faces], wall_u=wall_u)
+    f0 = inputs.random_populations(q, *dims, seed=8)
+    lat.set_f(f0)
+    lat.step(3)  # first snapshot at t = 3
+    lat.step(3)  # second at t = 6
+    r = lat.residual()
+    m = lat.mass()
+    f3 = R.run(pr, f0, 0, 3)
+    f6 = R.run(pr, f3, 3, 3)
+    _, u3 = R.macros(pr, f3, 3)
+    _, u6 = R.macros(pr, f6, 6)
+    r_ref = np.sum(np.abs(u6 - u3)) / (3 * np.sum(np.abs(u6)))
+    assert abs(r - r_ref) <= 1e-12 * r_ref
+    assert abs(m - f6.sum()) <= 1e-13 * np.abs(f6).sum()
+    lat.close()
+
+
+def test_nonfinite_is_reported():
+    """A NaN injected through set_f surfaces as LBM_ENONFINITE (host-forced)."""
+    q, dims = 18, (16, 8, 8)
+    lat = lbm.Lattice(q, *dims, rates(q), faces=FACESETS["cavity"], monitor_every=2)
+    f = inputs.random_populations(q, *dims, seed=9)
+    f[3, 4, 4, 4] = np.nan
+    lat.set_f(f)
+    lat.step(2)
+    with pytest.raises(lbm.LbmError) as e:
+        lat.residual()
+    assert e.value.code == -4
+    lat.close()
+
+
+# ---- full-size workload: 128^3 lid-driven cavity, D3Q18, FP32, AA ---------
+
+def cavity128(q=18, storage="f32"):
+    nu = 0.1 * 128 / 1000.0
+    s = svec(q, 1.0 / (3 * nu + 0.5))
+    lat = lbm.Lattice(q, 128, 128, 128, s, faces=FACESETS["cavity"], wall_u={"+z": (0.1, 0, 0)},
+                      storage=storage, pattern="aa")
+    pr = R.problem(q, 128, 128, 128, s, faces=FACESETS["cavity"], wall_u={"+z": (0.1, 0, 0)})
+    return lat, pr
+
+
+def test_full_size_cavity_random_state_two_steps():
+    lat, pr = cavity128()
+    f0 = inputs.random_populations(18, 128, 128, 128, seed=10)
+    lat.set_f(f0)
+    f0 = lat.get_f()
+    lat.step(2)
+    ref = R.run(pr, f0, 0, 2)
+    got = lat.get_f()
+    assert rel_l2(got, ref) <= 1e-6
+    p, u = lat.macros()
+    pr_, ur_ = R.macros(pr, ref, 2)
+    assert rel_l2(u, ur_) <= 1e-5
+    lat.close()
+
+
+def test_full_size_cavity_properties_after_2000_steps():
+    """Lid along +x: mirror symmetry in y (u_y odd, u_x and u_z even) and
+    conserved mass (tangential lid) hold at any size."""
+    lat, _ = cavity128()
+    lat.monitor()
+    m0 = lat.mass()
+    lat.step(2000)
+    lat.monitor()
+    m1 = lat.mass()
+    p, u = lat.macros()
+    assert np.all(np.isfinite(u))
+    umax = np.max(np.abs(u))
+    assert 0.01 < umax < 0.2
+    mir = u[:, :, ::-1, :]
+    assert np.max(np.abs(u[0] - mir[0])) <= 1e-5 * umax
+    assert np.max(np.abs(u[1] + mir[1])) <= 1e-5 * umax
+    assert np.max(np.abs(u[2] - mir[2])) <= 1e-5 * umax
+    assert abs(m1 - m0) <= 1e-6 * 128 ** 3 * 0.01
+    lat.close()
