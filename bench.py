@@ -173,11 +173,8 @@ def main():
         "copy_probe_GBs": round(copy_gbs, 1),
     }
     if not args.no_serving:
-        try:
-            from paper_1503_03337_amd import serve
-            out["serving"] = serve.bench_summary(torch)
-        except ImportError:
-            out["serving"] = None
+        from paper_1503_03337_amd import serve
+        out["serving"] = serve.bench_summary()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

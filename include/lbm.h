@@ -69,6 +69,16 @@ typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
 
 typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_face_kind;
 
+/* Rounding of LBM_F16DEV stores made by a time step.  Stochastic (the
+ * default): a value rounds up with probability equal to its distance from
+ * the lower FP16 neighbour, with random bits from a hash of (node,
+ * population, time level) -- deterministic and unbiased, so increments below
+ * half an FP16 ulp survive on average; the price is a small stationary
+ * fluctuation (a residual floor of order 1e-6).  Nearest: round to nearest
+ * even; a steady state is reached exactly but slow weak forcing stagnates.
+ * lbm_set_f and initialisation always round to nearest. */
+typedef enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_NEAREST = 1 } lbm_rounding;
+
 typedef enum {
   LBM_OK = 0,
   LBM_EINVAL = -1,     /* bad argument: q, dims < 1, N >= 2^31, s_k outside [0,2),
@@ -91,6 +101,7 @@ typedef struct {
   int storage;          /* lbm_storage                                       */
   int pattern;          /* lbm_pattern                                       */
   int f16_scale_log2;   /* s of LBM_F16DEV, 0..24                           */
+  int f16_rounding;     /* lbm_rounding of LBM_F16DEV step stores            */
   int monitor_every;    /* K > 0: run the mass/residual monitor every K steps */
   void* stream;         /* hipStream_t to queue work on (NULL: null stream)  */
   void* dev_buf;        /* optional caller-owned device buffer ...           */
@@ -98,7 +109,8 @@ typedef struct {
 } lbm_spec;
 
 /* Defaults: all six faces walls at rest, no force, p0 = 0, u0 = 0, FP32,
- * AA pattern, f16_scale_log2 = 12, no monitor, null stream, own memory. */
+ * AA pattern, f16_scale_log2 = 12, stochastic FP16 rounding, no monitor,
+ * null stream, own memory. */
 void lbm_spec_default(lbm_spec* spec);
 
 /* Device bytes a context of this shape needs (populations, monitor
@@ -187,8 +199,9 @@ int lbm_batch_remove(lbm_batch* b, lbm_ctx* ctx);
  * (0,0 = automatic). */
 int lbm_batch_set_tile(lbm_batch* b, lbm_ctx* ctx, int tx, int ty);
 int lbm_batch_step(lbm_batch* b, long long n);
-/* Run every member's monitor (one launch); then lbm_residual / lbm_mass of
- * each member read its values. */
+/* Run the monitor of every member created with monitor_every > 0 (one
+ * launch; synchronises the stream); then lbm_residual / lbm_mass of each
+ * such member read its values.  Members without a monitor are skipped. */
 int lbm_batch_monitor(lbm_batch* b);
 /* Remaining step budget of a member (0 when done); -1 if not a member. */
 long long lbm_batch_remaining(const lbm_batch* b, const lbm_ctx* ctx);

@@ -1,0 +1,73 @@
+"""Tile-shape autotuner for batched execution.
+
+A workgroup of the batched kernel covers a tx x ty tile of one x-y plane of
+its member (tx * ty <= 256 threads).  The best shape depends on the edge
+length (full rows keep each wavefront on contiguous memory; short rows
+waste lanes unless several rows share a workgroup) and on q.  For every
+(q, edge bucket) present in a batch the tuner times each candidate tile on a
+small batch of that bucket's members and keeps the fastest.  The tile never
+changes results (each node's arithmetic is the same), only speed.
+"""
+import time
+
+from . import lbm
+
+
+def candidates(edge):
+    """Tile shapes worth trying for rows of `edge` nodes."""
+    out = []
+    if edge <= 256:
+        out.append((edge, max(1, min(edge, 256 // edge))))
+    for tx in (256, 128, 64, 32, 16):
+        if tx <= max(16, 2 * edge):
+            out.append((tx, max(1, 256 // tx)))
+    seen, uniq = set(), []
+    for t in out:
+        if t not in seen:
+            seen.add(t)
+            uniq.append(t)
+    return uniq
+
+
+def bucket(edge, width=8):
+    return (edge // width) * width
+
+
+def tune(make_lattice, keys, steps=40, reps=2, stream=None, sync=None):
+    """keys: iterable of (q, edge).  make_lattice(q, edge) returns a fresh
+    lbm.Lattice (FP32 or FP16DEV, AA).  Returns {(q, bucket(edge)): (tx, ty)}
+    and the measured MLUPS per candidate."""
+    import torch
+    best, log = {}, {}
+    groups = {}
+    for q, edge in keys:
+        groups.setdefault((q, bucket(edge)), []).append(edge)
+    for (q, bk), edges in sorted(groups.items()):
+        sample = sorted(edges)[len(edges) // 2]
+        lats = [make_lattice(q, sample) for _ in range(4)]
+        nodes = sum(l.N for l in lats)
+        results = {}
+        for tile in candidates(sample):
+            b = lbm.Batch(lats[0].stream)
+            for l in lats:
+                b.add(l, 10 ** 9)
+                b.set_tile(l, *tile)
+            b.step(4)
+            torch.cuda.synchronize()
+            t = float("inf")
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                b.step(steps)
+                torch.cuda.synchronize()
+                t = min(t, time.perf_counter() - t0)
+            b.close()
+            results[tile] = nodes * steps / t / 1e6
+        for l in lats:
+            l.close()
+        best[(q, bk)] = max(results, key=results.get)
+        log[(q, bk)] = results
+    return best, log
+
+
+def tile_for(table, q, edge):
+    return table.get((q, bucket(edge)))

@@ -32,6 +32,33 @@ namespace lbm {
 // earlier, unrelated runtime call left behind so only this launch counts.
 static inline void clear_stale_error() { (void)hipGetLastError(); }
 
+// ---- population memory access --------------------------------------------------
+// Every population value is touched once per step.  The AB pattern reads a
+// copy it never writes in the same step: its loads carry the non-temporal
+// hint (measured +20 % on 128^3 D3Q18 FP32).  The AA pattern reads lines it
+// writes back right after, where the hint costs ~20 %, so it loads
+// normally.  LBM_NT_LOAD forces the hint on every load, LBM_NT_STORE on
+// every store (both measured neutral or worse).
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 0
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+template <bool NT, typename S>
+__device__ __forceinline__ S pop_load(const S* p) {
+  if (NT || LBM_NT_LOAD) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <typename S>
+__device__ __forceinline__ void pop_store(S* p, S v) {
+#if LBM_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 // ---- storage codecs --------------------------------------------------------
 template <int ST> struct Codec;
 template <> struct Codec<ST_F64> {
@@ -47,6 +74,15 @@ template <> struct Codec<ST_F32> {
   static __device__ __forceinline__ S enc(C v, C, C) { return v; }
 };
 // FP16 deviation: stored h = fp16((f - base) 2^s); 2^s and 2^-s are exact.
+// enc rounds to nearest.  enc_sr rounds stochastically: r holds 13 random
+// bits, added to the 13 FP32 mantissa bits that FP16 drops before
+// truncating, so the value rounds up with probability equal to its distance
+// from the lower FP16 neighbour (unbiased).  Round-to-nearest applied to a
+// nearly steady state rounds the same values the same way every step, and
+// increments below half an FP16 ulp (a weak body force, a slow viscous
+// correction) are lost every time; the stochastic form keeps them on
+// average.  Values below FP16's normal range (|h| < 2^-14) and near its top
+// round to nearest.
 template <> struct Codec<ST_F16> {
   using S = _Float16;
   using C = float;
@@ -56,7 +92,49 @@ template <> struct Codec<ST_F16> {
   static __device__ __forceinline__ S enc(C v, C base, C scale) {
     return static_cast<_Float16>((v - base) * scale);
   }
+  static __device__ __forceinline__ S enc_sr(C v, C base, C scale, unsigned r) {
+    float x = (v - base) * scale;
+    const unsigned u = __float_as_uint(x);
+    unsigned mag = u & 0x7fffffffu;
+    if (mag >= 0x38800000u && mag < 0x477fe000u) {  // [2^-14, 65504)
+      mag = (mag + (r & 0x1fffu)) & ~0x1fffu;
+      x = __uint_as_float((u & 0x80000000u) | mag);  // exactly an FP16 value
+    }
+    return static_cast<_Float16>(x);
+  }
 };
+
+// Counter-based random bits for the FP16 dither: a hash of (node, time
+// level), then one mixing step per population.  Deterministic, so a lattice
+// gives the same bits alone or in a batch, in either memory pattern.
+__device__ __forceinline__ unsigned node_hash(unsigned n, unsigned t) {
+  unsigned x = (n * 0x9E3779B1u) ^ (t * 0x85EBCA77u + 0x165667B1u);
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ unsigned pop_bits(unsigned h, int a) {
+  unsigned x = h ^ (0x9E3779B9u * (unsigned)(a + 1));
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
+  x *= 0xC2B2AE35u;
+  return x >> 19;  // 13 bits
+}
+
+// Encode a post-collision value: FP16 with the step's rounding mode, the
+// other storages plainly.
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::S enc_step(const LatticeArgs<typename Codec<ST>::C>& A,
+                                                          typename Codec<ST>::C v, int slot,
+                                                          unsigned h, int a) {
+  if constexpr (ST == ST_F16) {
+    if (A.f16_sr) return Codec<ST>::enc_sr(v, A.base[slot], A.scale, pop_bits(h, a));
+  }
+  return Codec<ST>::enc(v, A.base[slot], A.scale);
+}
 
 // ---- neighbour offsets -----------------------------------------------------
 // For each axis and direction (-1, +1): the linear-index delta of the
@@ -134,7 +212,7 @@ __device__ __forceinline__ void link(const Nbr& b, const LatticeArgs<C>& A, int 
 // an even step: f_a(x) = A[abar][x - c_a], or, when x - c_a is a wall,
 // A[a][x], where the even step already stored the bounced-back value
 // f*_abar(x) - 6 w_abar (c_abar . u_w).
-template <int Q, int ST, int PHASE, bool GEN>
+template <int Q, int ST, int PHASE, bool GEN, bool NT = false>
 __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::C>& A,
                                           const typename Codec<ST>::S* src, unsigned n, int x,
                                           int y, int z, typename Codec<ST>::C (&f)[Q]) {
@@ -144,7 +222,8 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
   const long long st = A.stride;
   if (PHASE == 0) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) f[a] = CD::dec(src[a * st + n], A.base[a], A.inv_scale);
+    for (int a = 0; a < Q; ++a)
+      f[a] = CD::dec(pop_load<NT>(src + a * st + n), A.base[a], A.inv_scale);
   } else {
     const Nbr b = make_nbr<GEN>(A, x, y, z);
 #pragma unroll
@@ -155,7 +234,7 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
       C term;
       link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term);
       const long long idx = wall ? (a * st + n) : (o * st + (long long)(n + off));
-      f[a] = CD::dec(src[idx], A.base[a], A.inv_scale);
+      f[a] = CD::dec(pop_load<NT>(src + idx), A.base[a], A.inv_scale);
     }
   }
 }
@@ -173,6 +252,8 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
   using C = typename CD::C;
   using L = Lattice<Q>;
   const long long st = A.stride;
+  // dither bits of the value population a leaves this node with at level t
+  const unsigned h = (ST == ST_F16) ? node_hash(n, A.tstep) : 0u;
   if (MODE == MODE_AA_EVEN) {
     const Nbr b = make_nbr<GEN>(A, x, y, z);
 #pragma unroll
@@ -182,7 +263,7 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       bool wall;
       C term;
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term);
-      dst[o * st + n] = CD::enc(wall ? f[a] - term : f[a], A.base[o], A.scale);
+      pop_store(dst + o * st + n, enc_step<ST>(A, wall ? f[a] - term : f[a], o, h, a));
     }
   } else {
     const Nbr b = make_nbr<GEN>(A, x, y, z);
@@ -194,9 +275,9 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       C term;
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term);
       if (wall)
-        dst[o * st + n] = CD::enc(f[a] - term, A.base[o], A.scale);
+        pop_store(dst + o * st + n, enc_step<ST>(A, f[a] - term, o, h, a));
       else
-        dst[a * st + (long long)(n + off)] = CD::enc(f[a], A.base[a], A.scale);
+        pop_store(dst + a * st + (long long)(n + off), enc_step<ST>(A, f[a], a, h, a));
     }
   }
 }
@@ -211,7 +292,7 @@ __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::
   const unsigned n = (unsigned)x + (unsigned)A.nx * ((unsigned)y + (unsigned)A.ny * (unsigned)z);
   C f[Q];
   if (MODE == MODE_AB) {
-    read_node<Q, ST, 0, GEN>(A, static_cast<const S* __restrict__>(A.f), n, x, y, z, f);
+    read_node<Q, ST, 0, GEN, true>(A, static_cast<const S*>(A.f), n, x, y, z, f);
   } else if (MODE == MODE_AA_EVEN) {
     read_node<Q, ST, 0, GEN>(A, static_cast<const S*>(A.f), n, x, y, z, f);
   } else {
@@ -635,18 +716,30 @@ hipError_t launch_reduce_partials(const double* partial, int nb, double* out, hi
 }
 
 // ---- measurement helper: plain streaming copy ---------------------------------
+// Each thread moves 4 x 16 bytes, all four loads issued before the stores,
+// one workgroup per 16 KB: the achievable-bandwidth reference.
 __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
                                               uint4* __restrict__ dst, long long n16) {
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n16; i += (long long)gridDim.x * 256)
-    dst[i] = src[i];
+  const long long base = blockIdx.x * 1024LL + threadIdx.x;
+  uint4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long i = base + 256LL * k;
+    if (i < n16) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long i = base + 256LL * k;
+    if (i < n16) dst[i] = v[k];
+  }
 }
 
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s) {
   clear_stale_error();
   const long long n16 = (long long)(bytes / 16);
-  long long nb = (n16 + 255) / 256;
-  if (nb > 256 * 64) nb = 256 * 64;
+  long long nb = (n16 + 1023) / 1024;
   if (nb < 1) nb = 1;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, (const uint4*)src, (uint4*)dst,
                      n16);
   return hipGetLastError();
@@ -664,6 +757,7 @@ __device__ __forceinline__ void batch_node(const BatchMember& m, int phase, cons
                                            int substep, int x, int y, int z) {
   if (ST == ST_F32) {
     LatticeArgs<float> A = m.a;
+    A.tstep = m.a.tstep + (unsigned)substep;
     if (FORCED) {
       const float* Fr = ftab + m.ftab_off + 3LL * substep;
       A.F[0] = Fr[0];
@@ -676,6 +770,7 @@ __device__ __forceinline__ void batch_node(const BatchMember& m, int phase, cons
       node_step_any<Q, ST_F32, MODE_AA_ODD, FORCED>(A, x, y, z);
   } else {
     LatticeArgs<float> A = m.a;
+    A.tstep = m.a.tstep + (unsigned)substep;
     if (FORCED) {
       const float* Fr = ftab + m.ftab_off + 3LL * substep;
       A.F[0] = Fr[0];

@@ -26,6 +26,8 @@ template <typename C> struct LatticeArgs {
   C F[3];                  // body force at this step
   C base[18];              // FP16 deviation base 3 w_a p0
   C scale, inv_scale;      // FP16 2^s, 2^-s
+  unsigned tstep;          // time level t of this step (FP16 rounding dither)
+  int f16_sr;              // FP16 stores: 1 stochastic rounding, 0 nearest
 };
 
 // Launches (all asynchronous on `stream`; return a hipError_t).

@@ -35,8 +35,19 @@ size_t monitor_bytes(size_t N, int storage) {
   return align_up(snap) + align_up(3 * sizeof(double) * 2048) + align_up(4 * sizeof(double));
 }
 
+// Elements between consecutive population arrays: N rounded up to 64 (a
+// wavefront's worth) plus LBM_STRIDE_PAD elements.  Without the pad, the q
+// arrays of a power-of-two lattice start at power-of-two offsets and the q
+// streams of one wavefront hit the same memory channels; 1088 elements
+// (4352 B in FP32) shift each array by a little over one 4 KB interleave
+// step (measured +4 % on 128^3 D3Q18 FP32 AA; neutral at 256^3).
+#ifndef LBM_STRIDE_PAD
+#define LBM_STRIDE_PAD 1088
+#endif
+size_t pop_stride(size_t N) { return (N + 63) / 64 * 64 + LBM_STRIDE_PAD; }
+
 size_t population_bytes(int q, size_t N, int storage) {
-  return (size_t)q * N * (size_t)bytes_of(storage);
+  return (size_t)q * pop_stride(N) * (size_t)bytes_of(storage);
 }
 
 std::string validate(int model, int nx, int ny, int nz, const double* s, const lbm_spec* sp) {
@@ -50,6 +61,8 @@ std::string validate(int model, int nx, int ny, int nz, const double* s, const l
   if (sp->storage == LBM_F16DEV && (sp->f16_scale_log2 < 0 || sp->f16_scale_log2 > 24))
     return "f16_scale_log2 must be in 0..24";
   if (sp->monitor_every < 0) return "monitor_every must be >= 0";
+  if (sp->f16_rounding != LBM_ROUND_STOCHASTIC && sp->f16_rounding != LBM_ROUND_NEAREST)
+    return "unknown f16_rounding";
   for (int d = 0; d < 3; ++d) {
     const int a = sp->face[2 * d], b = sp->face[2 * d + 1];
     if ((a != LBM_PERIODIC && a != LBM_WALL) || (b != LBM_PERIODIC && b != LBM_WALL))
@@ -163,7 +176,7 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
   std::memset(&A, 0, sizeof(A));
   A.f = c.popA;
   A.g = c.popB ? c.popB : c.popA;
-  A.stride = (long long)c.N;
+  A.stride = (long long)pop_stride(c.N);
   A.nx = c.nx;
   A.ny = c.ny;
   A.nz = c.nz;
@@ -197,6 +210,8 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
   A.scale = (C)sc;
   A.inv_scale = (C)(1.0 / sc);
   A.F[0] = A.F[1] = A.F[2] = 0;
+  A.tstep = (unsigned)c.t;
+  A.f16_sr = c.spec.f16_rounding == LBM_ROUND_STOCHASTIC ? 1 : 0;
 }
 
 void refresh_args(lbm_ctx& c) {
@@ -208,6 +223,7 @@ const void* args_ptr(lbm_ctx& c) {
   return c.spec.storage == LBM_F64 ? (const void*)&c.a64 : (const void*)&c.a32;
 }
 
+// Per-step kernel arguments: the force F(t) and the time level t.
 void set_force(lbm_ctx& c, long long t) {
   double F[3];
   force_at(c.spec, t, F);
@@ -215,6 +231,7 @@ void set_force(lbm_ctx& c, long long t) {
     c.a64.F[d] = F[d];
     c.a32.F[d] = (float)F[d];
   }
+  c.a64.tstep = c.a32.tstep = (unsigned)t;
 }
 
 void pick_tile(int nx, int ny, int& tx, int& ty) {
@@ -781,11 +798,16 @@ int lbm_batch_step(lbm_batch* b, long long n) {
 
 int lbm_batch_monitor(lbm_batch* b) {
   if (!b) return LBM_EINVAL;
-  const int nm = (int)b->members.size();
+  // members created with monitor_every > 0 (their footprint holds the
+  // monitor scratch)
+  std::vector<lbm_ctx*> mons;
+  for (auto& m : b->members)
+    if (m.ctx->spec.monitor_every > 0) mons.push_back(m.ctx);
+  const int nm = (int)mons.size();
   if (nm == 0) return LBM_OK;
-  for (auto& m : b->members) {
-    int rc = ensure_monitor(m.ctx);
-    if (rc) return bfail(b, rc, m.ctx->err);
+  for (lbm_ctx* c : mons) {
+    int rc = ensure_monitor(c);
+    if (rc) return bfail(b, rc, c->err);
   }
   // layout of the staging block: members | snaps | pofs | bbeg | pcount |
   // phases | partials | out
@@ -795,7 +817,7 @@ int lbm_batch_monitor(lbm_batch* b) {
   std::vector<int> phases(nm);
   long long blocks = 0;
   for (int j = 0; j < nm; ++j) {
-    lbm_ctx* c = b->members[j].ctx;
+    lbm_ctx* c = mons[j];
     std::memset(&hm[j], 0, sizeof(BatchMember));
     fill_args<float>(*c, hm[j].a);
     double F[3];
@@ -844,7 +866,7 @@ int lbm_batch_monitor(lbm_batch* b) {
   BHIP(b, hipMemcpyAsync(res.data(), d + o_out, 3 * nm * sizeof(double), hipMemcpyDeviceToHost, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
   for (int j = 0; j < nm; ++j) {
-    lbm_ctx* c = b->members[j].ctx;
+    lbm_ctx* c = mons[j];
     c->mon[0] = res[3 * j];
     c->mon[1] = res[3 * j + 1];
     c->mon[2] = res[3 * j + 2];

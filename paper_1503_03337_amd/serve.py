@@ -5,33 +5,43 @@ budget or a stop at a velocity residual) arrive over time.  Two servers:
 
   plain    one request at a time, in arrival order, FP32 storage, the
            single-lattice kernel (lbm_step)
-  batched  continuous batching: arrived requests are admitted while their
-           HBM footprint (lbm_footprint_bytes) fits the budget; all admitted
-           requests advance together, one kernel launch per time step
-           (lbm_batch_step) in quanta of Q steps; between quanta finished
-           requests retire (freeing memory) and waiting ones are admitted.
-           Storage FP32 or FP16 deviations.
+  batched  continuous batching: arrived requests are admitted, in arrival
+           order, while their HBM footprint (lbm_footprint_bytes) fits the
+           budget; all admitted requests advance together, one kernel launch
+           per time step (lbm_batch_step), in quanta of Q steps; between
+           quanta finished requests retire (freeing their memory) and
+           waiting ones are admitted, so new work overlaps running work on
+           the device.  Storage FP32 or FP16 deviations.
 
-Latency is arrival -> finish; aggregate throughput is the node updates of
-all requests divided by the time from first arrival to last finish.
+Latency is arrival -> finish.  Aggregate throughput is the node updates of
+all requests over the time from the first arrival to the last finish.
 """
+import math
 import time
 
 import numpy as np
 
-from . import inputs, lbm, params
+from . import autotune, inputs, lbm, params
 
-MONITOR_EVERY = 100      # residual lag (steps) for requests with a residual stop
-DUCT_NU = 0.1            # duct viscosity (lattice units); u_max = 0.05
-CAVITY_RE = 400.0        # cavity Reynolds number at lid speed 0.1
+MONITOR_EVERY = 100   # residual lag (steps) for requests with a residual stop
+DUCT_UMAX = 0.05      # centre-line speed of duct requests
+CAVITY_RE = 400.0     # cavity Reynolds number at lid speed 0.1
+DUCT_EFOLD = 1500.0   # slowest duct mode decays within this many steps
+
+
+def duct_nu(edge):
+    """Viscosity of a duct request: 0.1, or more for wide ducts so that the
+    slowest mode, rate nu (pi/2a)^2 2, e-folds within DUCT_EFOLD steps."""
+    a = edge / 2.0
+    return max(0.1, a * a / (2.0 * (math.pi / 2.0) ** 2 * DUCT_EFOLD))
 
 
 def request_setup(req):
-    """Lattice description of a request: a square duct (x periodic, edge^3
-    nodes, body force for u_max = 0.05) or a lid-driven cube."""
+    """Lattice of a request: a square duct (edge^3 nodes, x periodic, body
+    force for u_max = 0.05) or a lid-driven cube (lid 0.1 along +x)."""
     q, L = req["q"], req["edge"]
     if req["kind"] == "duct":
-        cfg = params.duct(q, L, L, DUCT_NU, umax=0.05)
+        cfg = params.duct(q, L, L, duct_nu(L), umax=DUCT_UMAX)
         kw = {"faces": cfg["faces"], "F0": cfg["F0"]}
     else:
         cfg = params.cavity(q, L, CAVITY_RE, lid=0.1)
@@ -39,24 +49,25 @@ def request_setup(req):
     return cfg["s_vec"], kw
 
 
+def _monitor(req):
+    return MONITOR_EVERY if req.get("stop_residual") else 0
+
+
 def footprint(req, storage):
-    s, kw = request_setup(req)
-    mon = MONITOR_EVERY if req.get("stop_residual") else 0
-    return lbm.footprint_bytes(req["q"], req["edge"], req["edge"], req["edge"], storage=storage,
-                               pattern="aa", monitor_every=mon, **kw)
+    _, kw = request_setup(req)
+    L = req["edge"]
+    return lbm.footprint_bytes(req["q"], L, L, L, storage=storage, pattern="aa",
+                               monitor_every=_monitor(req), **kw)
 
 
 def make_lattice(req, storage):
     s, kw = request_setup(req)
     L = req["edge"]
-    mon = MONITOR_EVERY if req.get("stop_residual") else 0
-    return lbm.Lattice(req["q"], L, L, L, s, storage=storage, pattern="aa", monitor_every=mon,
-                       **kw)
+    return lbm.Lattice(req["q"], L, L, L, s, storage=storage, pattern="aa",
+                       monitor_every=_monitor(req), **kw)
 
 
 class Clock:
-    """Trace time: seconds since the server started."""
-
     def __init__(self):
         self.t0 = time.perf_counter()
 
@@ -72,13 +83,14 @@ def _finish(rec, clock, lat, keep_fields):
         rec["u"] = lat.macros()[1]
 
 
-def serve_plain(trace, storage="f32", keep_fields=False, sync=None):
-    """One request at a time in arrival order (FIFO)."""
+def serve_plain(trace, storage="f32", keep_fields=False):
+    """One request at a time in arrival order (FIFO), lbm_step."""
+    import torch
     clock = Clock()
     out = []
     for req in sorted(trace, key=lambda r: r["arrival"]):
         while clock.now() < req["arrival"]:
-            time.sleep(min(0.001, req["arrival"] - clock.now()))
+            time.sleep(min(0.001, max(0.0, req["arrival"] - clock.now())))
         rec = dict(req)
         rec["admit"] = clock.now()
         lat = make_lattice(req, storage)
@@ -93,55 +105,54 @@ def serve_plain(trace, storage="f32", keep_fields=False, sync=None):
                         break
         else:
             lat.step(req["steps"])
-        lat.sync()
+        torch.cuda.current_stream().synchronize()
         _finish(rec, clock, lat, keep_fields)
         lat.close()
         out.append(rec)
-    return out
+    return out, {"peak_bytes": max(footprint(r, storage) for r in trace)}
 
 
-def serve_batched(trace, storage="f16dev", budget_bytes=None, quantum=100, keep_fields=False,
-                  tiles=None):
-    """Continuous batching with admission by HBM footprint."""
+def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
+                  keep_fields=False, tiles=None):
+    """Continuous batching with admission by HBM footprint.
+
+    tiles: optional {(q, edge bucket): (tx, ty)} from autotune.tune."""
     import torch
-    if budget_bytes is None:
-        free, _ = torch.cuda.mem_get_info()
-        budget_bytes = int(0.8 * free)
     clock = Clock()
     pending = sorted(trace, key=lambda r: r["arrival"])
-    stream = torch.cuda.current_stream().cuda_stream
-    batch = lbm.Batch(stream)
-    active = []  # (rec, lattice)
-    used = 0
+    batch = lbm.Batch(torch.cuda.current_stream().cuda_stream)
+    active = []  # (record, lattice)
+    used = peak = 0
+    launches = 0
     out = []
     while pending or active:
-        # admit whatever has arrived and fits
         now = clock.now()
         while pending and pending[0]["arrival"] <= now:
             need = footprint(pending[0], storage)
             if need > budget_bytes:
-                raise ValueError("request %d needs %d bytes, above the budget" %
-                                 (pending[0]["id"], need))
+                raise ValueError("request %d needs %d bytes, above the budget %d" %
+                                 (pending[0]["id"], need, budget_bytes))
             if used + need > budget_bytes:
-                break
+                break  # wait for memory: admitted in arrival order
             req = pending.pop(0)
             rec = dict(req)
             rec["admit"] = clock.now()
             lat = make_lattice(req, storage)
             batch.add(lat, req["steps"])
-            if tiles is not None:
-                t = tiles.get((req["q"], req["edge"]))
+            if tiles:
+                t = autotune.tile_for(tiles, req["q"], req["edge"])
                 if t:
                     batch.set_tile(lat, *t)
             rec["_need"] = need
             used += need
+            peak = max(peak, used)
             active.append((rec, lat))
         if not active:
-            # idle: wait for the next arrival
             if pending:
                 time.sleep(max(0.0, min(0.001, pending[0]["arrival"] - clock.now())))
             continue
         batch.step(quantum)
+        launches += quantum
         if any(r.get("stop_residual") for r, _ in active):
             batch.monitor()  # synchronises
         else:
@@ -161,37 +172,93 @@ def serve_batched(trace, storage="f16dev", budget_bytes=None, quantum=100, keep_
                 keep.append((rec, lat))
         active = keep
     batch.close()
-    return out
+    return out, {"peak_bytes": peak, "budget_bytes": budget_bytes, "step_launches": launches}
 
 
-def summarise(records):
+def summarise(records, extra=None):
     lat = np.array([r["latency"] for r in records])
     nodes = sum(r["edge"] ** 3 * r["steps_done"] for r in records)
     t0 = min(r["arrival"] for r in records)
     t1 = max(r["finish"] for r in records)
-    return {"requests": len(records),
-            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "aggregate_MLUPS": nodes / (t1 - t0) / 1e6, "makespan_s": t1 - t0}
+    out = {"requests": len(records),
+           "p50_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_s": round(float(np.percentile(lat, 99)), 4),
+           "aggregate_MLUPS": round(nodes / (t1 - t0) / 1e6, 1),
+           "makespan_s": round(t1 - t0, 3)}
+    if extra:
+        out.update({k: v for k, v in extra.items()})
+    return out
 
 
-def bench_summary(torch, n=24, seed=1, rate=None):
-    """Plain FP32 against batched FP16-deviation (and FP32) on one seeded
-    trace, for the benchmark line.  `rate` defaults to ~0.8x the plain
-    server's measured capacity on a probe."""
-    probe = inputs.serving_trace(4, rate=1e9, seed=seed + 100, edge=(64, 96), steps=(2000, 3000),
-                                 p_residual=0.0)
-    pr = serve_plain(probe)
-    svc = np.mean([r["finish"] - r["admit"] for r in pr])
+def duct_error(records, series):
+    """max over duct requests of max_nodes |u - u_series| / u_max, with
+    series(y, z, a, g, nu) the steady duct solution."""
+    worst = 0.0
+    for r in records:
+        if r["kind"] != "duct" or "u" not in r:
+            continue
+        L = r["edge"]
+        a = L / 2.0
+        nu = duct_nu(L)
+        g = DUCT_UMAX * nu / (params.DUCT_UMAX_COEFF * a * a)
+        y = np.arange(L) + 0.5 - a
+        Y, Z = np.meshgrid(y, y, indexing="xy")
+        ua = series(Y, Z, a, g, nu)
+        ux = r["u"][0]
+        worst = max(worst, float(np.max(np.abs(ux - ua[:, :, None])) / DUCT_UMAX))
+    return worst
+
+
+def bench_summary(n=24, seed=1, budget_gib=16):
+    """Plain FP32 against batched FP32 and FP16 deviations on one seeded
+    Poisson trace (rate ~0.8x the plain server's measured capacity), and on
+    the same requests all arriving at once (saturated)."""
+    import torch
+    trace = inputs.serving_trace(n, rate=1.0, seed=seed)
+    # plain-server capacity from a short probe of the same request mix
+    probe = [dict(r, arrival=0.0, steps=max(200, r["steps"] // 10), stop_residual=None)
+             for r in trace[:6]]
+    pr, _ = serve_plain(probe)
     nodes_per_s = sum(r["edge"] ** 3 * r["steps_done"] for r in pr) / sum(
         r["finish"] - r["admit"] for r in pr)
-    trace = inputs.serving_trace(n, rate=1.0, seed=seed)
     mean_work = np.mean([r["edge"] ** 3 * r["steps"] for r in trace])
-    if rate is None:
-        rate = 0.8 * nodes_per_s / mean_work
+    rate = 0.8 * nodes_per_s / mean_work
     trace = inputs.serving_trace(n, rate=rate, seed=seed)
-    res = {"trace": {"requests": n, "rate_per_s": rate, "seed": seed,
-                     "probe_service_s": float(svc)}}
-    res["plain_f32"] = summarise(serve_plain(trace, "f32"))
-    res["batched_f32"] = summarise(serve_batched(trace, "f32"))
-    res["batched_f16dev"] = summarise(serve_batched(trace, "f16dev"))
+    from . import autotune as at
+    keys = {(r["q"], r["edge"]) for r in trace}
+
+    def mk(q, edge):
+        return make_lattice({"q": q, "edge": edge, "kind": "cavity"}, "f32")
+    tiles, _ = at.tune(mk, keys, steps=20, reps=1)
+    budget = budget_gib << 30
+    res = {"trace": {"requests": n, "rate_per_s": round(rate, 3), "seed": seed,
+                     "budget_GiB": budget_gib}}
+    res["plain_f32"] = summarise(*serve_plain(trace, "f32"))
+    res["batched_f32"] = summarise(*serve_batched(trace, "f32", budget, tiles=tiles))
+    res["batched_f16dev"] = summarise(*serve_batched(trace, "f16dev", budget, tiles=tiles))
+    sat = [dict(r, arrival=0.0) for r in trace]
+    res["saturated_plain_f32"] = summarise(*serve_plain(sat, "f32"))
+    res["saturated_batched_f16dev"] = summarise(*serve_batched(sat, "f16dev", budget,
+                                                               tiles=tiles))
+    res["duct_accuracy"] = duct_accuracy()
+    torch.cuda.synchronize()
     return res
+
+
+def duct_accuracy(edges=(32, 64, 96), steps=20000):
+    """Converged duct requests (both models) served batched in FP16
+    deviations and plainly in FP32: max |u - u_series| / u_max."""
+    from . import duct_series
+    reqs = [{"id": i, "arrival": 0.0, "kind": "duct", "edge": L, "q": q, "steps": steps,
+             "stop_residual": None}
+            for i, (L, q) in enumerate((L, q) for L in edges for q in (14, 18))]
+    series = lambda Y, Z, a, g, nu: duct_series.velocity(Y, Z, a, a, g, nu)  # noqa: E731
+    b16, _ = serve_batched(reqs, "f16dev", keep_fields=True)
+    p32, _ = serve_plain(reqs, "f32", keep_fields=True)
+    return {"edges": list(edges), "steps": steps,
+            "max_err_over_umax_batched_f16dev": round(duct_error(b16, series), 6),
+            "max_err_over_umax_plain_f32": round(duct_error(p32, series), 6),
+            "max_f16_minus_f32_over_umax": round(max(
+                float(np.max(np.abs(a["u"] - b["u"]))) / DUCT_UMAX
+                for a, b in zip(sorted(b16, key=lambda r: r["id"]),
+                                sorted(p32, key=lambda r: r["id"]))), 6)}

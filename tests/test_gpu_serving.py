@@ -1,0 +1,83 @@
+"""Serving loop on the GPU: every request completes, admission never exceeds
+the HBM budget, each result is the same alone and in the mix, and served
+FP16-deviation duct solves stay within 1e-3 u_max of the FP32 ones and close
+to the analytic duct series (Sec. 4.1)."""
+import numpy as np
+import pytest
+
+from oracle import analytic
+from paper_1503_03337_amd import autotune, params, serve
+
+pytestmark = pytest.mark.gpu
+
+
+def small_trace():
+    reqs = []
+    rng = np.random.default_rng(5)
+    for i in range(8):
+        reqs.append({"id": i, "arrival": 0.002 * i, "kind": "duct" if i % 2 else "cavity",
+                     "edge": int(rng.integers(16, 41)), "q": 14 if i % 3 else 18,
+                     "steps": int(rng.integers(150, 450)),
+                     "stop_residual": 1e-3 if i in (2, 5) else None})
+    return reqs
+
+
+@pytest.mark.parametrize("storage", ("f32", "f16dev"))
+def test_mix_equals_alone_and_budget_respected(storage):
+    trace = small_trace()
+    fp = {r["id"]: serve.footprint(r, storage) for r in trace}
+    budget = sum(sorted(fp.values())[-3:])  # forces queueing
+    mixed, info = serve.serve_batched(trace, storage, budget_bytes=budget, quantum=50,
+                                      keep_fields=True)
+    assert len(mixed) == len(trace)
+    assert info["peak_bytes"] <= budget
+    by_id = {r["id"]: r for r in mixed}
+    for req in trace:
+        alone, _ = serve.serve_batched([dict(req, arrival=0.0)], storage, budget_bytes=budget,
+                                       quantum=50, keep_fields=True)
+        a, m = alone[0], by_id[req["id"]]
+        assert a["steps_done"] == m["steps_done"], req
+        if req["stop_residual"] is None:
+            assert m["steps_done"] == req["steps"]
+        assert np.array_equal(a["u"], m["u"]), req
+
+
+def test_plain_and_batched_agree():
+    trace = [r for r in small_trace() if r["stop_residual"] is None][:4]
+    plain, _ = serve.serve_plain(trace, "f32", keep_fields=True)
+    batched, _ = serve.serve_batched(trace, "f32", keep_fields=True)
+    bp = {r["id"]: r for r in plain}
+    for r in batched:
+        p = bp[r["id"]]
+        assert p["steps_done"] == r["steps_done"]
+        scale = max(np.max(np.abs(p["u"])), 1e-12)
+        assert np.max(np.abs(p["u"] - r["u"])) <= 1e-5 * scale
+
+
+def test_fp16_duct_accuracy():
+    reqs = [{"id": i, "arrival": 0.0, "kind": "duct", "edge": 32, "q": q, "steps": 12000,
+             "stop_residual": None} for i, q in enumerate((14, 18))]
+    b16, _ = serve.serve_batched(reqs, "f16dev", keep_fields=True)
+    p32, _ = serve.serve_plain(reqs, "f32", keep_fields=True)
+
+    def series(Y, Z, a, g, nu):
+        return analytic.duct_steady(Y, Z, a, a, g, nu)
+
+    e16 = serve.duct_error(b16, series)
+    e32 = serve.duct_error(p32, series)
+    d = max(np.max(np.abs(a["u"] - b["u"])) for a, b in
+            zip(sorted(b16, key=lambda r: r["id"]), sorted(p32, key=lambda r: r["id"])))
+    print("duct edge 32: max err/u_max FP16 %.2e FP32 %.2e, |FP16-FP32|/u_max %.2e"
+          % (e16, e32, d / serve.DUCT_UMAX))
+    assert d <= 1e-3 * serve.DUCT_UMAX
+    assert e32 < 1e-2 and e16 < 1e-2  # second-order bounce-back error at edge 32
+
+
+def test_autotune_picks_valid_tiles():
+    def mk(q, edge):
+        return serve.make_lattice({"q": q, "edge": edge, "kind": "cavity"}, "f32")
+    best, log = autotune.tune(mk, [(14, 24), (18, 40), (18, 45)], steps=10, reps=1)
+    assert set(best) == {(14, 24), (18, 40)}
+    for key, (tx, ty) in best.items():
+        assert 1 <= tx * ty <= 256
+        assert (tx, ty) in log[key]
