@@ -84,6 +84,62 @@ def copy_bandwidth(torch, lbm, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes / sec / 1e9
 
 
+def batch256(torch, lbm, params, steps=100):
+    """256 lid-driven cavities (edge U{24..96}, Re U[100,1000], D3Q14 or
+    D3Q18 at random, seed 0), FP32 AA, advanced together: one launch per
+    time step and (q, storage) class, tiles chosen by the autotuner."""
+    from paper_1503_03337_amd import autotune, inputs
+    spec = inputs.cavity_batch(256, seed=0)
+
+    def mk(q, edge):
+        cfg = params.cavity(q, edge, 400.0)
+        return lbm.Lattice(q, edge, edge, edge, cfg["s_vec"], faces=cfg["faces"],
+                           wall_u=cfg["wall_u"], storage="f32", pattern="aa")
+    tiles, _ = autotune.tune(mk, {(c["q"], c["edge"]) for c in spec}, steps=20, reps=1)
+    lats, b = [], lbm.Batch(torch.cuda.current_stream().cuda_stream)
+    for c in spec:
+        L = c["edge"]
+        cfg = params.cavity(c["q"], L, c["Re"], lid=c["lid"])
+        lat = lbm.Lattice(c["q"], L, L, L, cfg["s_vec"], faces=cfg["faces"],
+                          wall_u=cfg["wall_u"], storage="f32", pattern="aa")
+        b.add(lat, 10 ** 9)
+        t = autotune.tile_for(tiles, c["q"], L)
+        if t:
+            b.set_tile(lat, *t)
+        lats.append(lat)
+    nodes = sum(l.N for l in lats)
+    bytes_step = sum(2 * l.q * 4 * l.N for l in lats)
+    b.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    b.close()
+    for l in lats:
+        l.close()
+    return {"instances": len(spec), "nodes": nodes, "steps": steps,
+            "aggregate_MLUPS": round(nodes * steps / sec / 1e6, 1),
+            "achieved_GBs": round(bytes_step * steps / sec / 1e9, 1),
+            "hbm_frac": round(bytes_step * steps / sec / (HBM_PEAK_GBS * 1e9), 4)}
+
+
+def mrt_vs_lbgk(torch, lbm, params, n=128, steps=2000):
+    """The same 128^3 D3Q18 FP32 cavity with the MRT collision and with the
+    LBGK collision it reduces to for S = I/tau (Sec. 3): MLUPS of each."""
+    cfg = params.cavity(18, n, 1000.0, lid=0.1)
+    tau = 1.0 / cfg["s_vec"][8]
+    out = {}
+    for coll, s in (("mrt", cfg["s_vec"]), ("lbgk", [1.0 / tau] * 18)):
+        lat = lbm.Lattice(18, n, n, n, s, faces=cfg["faces"], wall_u=cfg["wall_u"],
+                          storage="f32", pattern="aa", collision="bgk" if coll == "lbgk" else "mrt")
+        lat.step(100)
+        wall, _ = time_steps(torch, lat, steps)
+        lat.close()
+        out[coll + "_MLUPS"] = round(n ** 3 * steps / wall / 1e6, 1)
+    return out
+
+
 def cpu_baseline(target_seconds=15.0):
     """The FP64 oracle on the host cores: 128^3 D3Q18 cavity from rest."""
     import numpy as np
@@ -147,6 +203,8 @@ def main():
     bwall, bev = time_steps(torch, big, bsteps)
     big.close()
     copy_gbs = copy_bandwidth(torch, lbm)
+    b256 = batch256(torch, lbm, params)
+    collisions = mrt_vs_lbgk(torch, lbm, params)
 
     out = {
         "metric": METRIC,
@@ -171,6 +229,8 @@ def main():
         "cavity256": {"MLUPS": round(256 ** 3 * bsteps / bwall / 1e6, 1),
                       "achieved_GBs": round(bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9, 1)},
         "copy_probe_GBs": round(copy_gbs, 1),
+        "batch256": b256,
+        "collision_cost": collisions,
     }
     if not args.no_serving:
         from paper_1503_03337_amd import serve

@@ -79,6 +79,14 @@ typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_face_kind;
  * lbm_set_f and initialisation always round to nearest. */
 typedef enum { LBM_ROUND_STOCHASTIC = 0, LBM_ROUND_NEAREST = 1 } lbm_rounding;
 
+/* Collision operator.  LBM_MRT: the moment-space collision above.  LBM_BGK:
+ * the single-relaxation-time special case S = I/tau that the MRT models
+ * reduce to (Sec. 3, Appendix B: the iD3Q15 / iD3Q19 LBGK models of Sec. 2),
+ * f*_a = f_a - (f_a - f_eq_a)/tau + (1 - 1/(2 tau)) w_a [3 c.F + 9 (c.u)(c.F)
+ * - 3 u.F], evaluated without the transforms; all q rates must be equal
+ * (tau = 1/s_vec[0]).  Single lattices only (batches are MRT). */
+typedef enum { LBM_MRT = 0, LBM_BGK = 1 } lbm_collision;
+
 typedef enum {
   LBM_OK = 0,
   LBM_EINVAL = -1,     /* bad argument: q, dims < 1, N >= 2^31, s_k outside [0,2),
@@ -102,6 +110,7 @@ typedef struct {
   int pattern;          /* lbm_pattern                                       */
   int f16_scale_log2;   /* s of LBM_F16DEV, 0..24                           */
   int f16_rounding;     /* lbm_rounding of LBM_F16DEV step stores            */
+  int collision;        /* lbm_collision                                     */
   int monitor_every;    /* K > 0: run the mass/residual monitor every K steps */
   void* stream;         /* hipStream_t to queue work on (NULL: null stream)  */
   void* dev_buf;        /* optional caller-owned device buffer ...           */
@@ -109,8 +118,8 @@ typedef struct {
 } lbm_spec;
 
 /* Defaults: all six faces walls at rest, no force, p0 = 0, u0 = 0, FP32,
- * AA pattern, f16_scale_log2 = 12, stochastic FP16 rounding, no monitor,
- * null stream, own memory. */
+ * AA pattern, f16_scale_log2 = 12, stochastic FP16 rounding, MRT collision,
+ * no monitor, null stream, own memory. */
 void lbm_spec_default(lbm_spec* spec);
 
 /* Device bytes a context of this shape needs (populations, monitor
@@ -177,6 +186,10 @@ typedef struct {
 int lbm_info(const lbm_ctx* ctx, lbm_info_t* info);
 
 int lbm_sync(lbm_ctx* ctx);                  /* wait for the context stream */
+/* lbm_destroy waits for the context stream only if it frees device memory
+ * the library allocated.  With a caller-owned spec.dev_buf it returns at
+ * once: work already queued on the stream may still use the buffer, so the
+ * caller must not reuse it out of stream order. */
 /* Message of the last failure on ctx; with ctx == NULL, of the last failed
  * lbm_create on the calling thread.  Never NULL. */
 const char* lbm_last_error(const lbm_ctx* ctx);

@@ -45,17 +45,24 @@ static inline void clear_stale_error() { (void)hipGetLastError(); }
 #ifndef LBM_NT_STORE
 #define LBM_NT_STORE 0
 #endif
+// Population pointers are always device global memory.  Saying so with the
+// address space lets the compiler use global (not flat) loads and stores
+// even when the pointer comes out of a descriptor in memory (the batched
+// kernels), which keeps the scalar-load and vector-memory counters apart.
+#define LBM_GLOBAL __attribute__((address_space(1)))
 template <bool NT, typename S>
 __device__ __forceinline__ S pop_load(const S* p) {
-  if (NT || LBM_NT_LOAD) return __builtin_nontemporal_load(p);
-  return *p;
+  const LBM_GLOBAL S* g = (const LBM_GLOBAL S*)p;
+  if (NT || LBM_NT_LOAD) return __builtin_nontemporal_load(g);
+  return *g;
 }
 template <typename S>
 __device__ __forceinline__ void pop_store(S* p, S v) {
+  LBM_GLOBAL S* g = (LBM_GLOBAL S*)p;
 #if LBM_NT_STORE
-  __builtin_nontemporal_store(v, p);
+  __builtin_nontemporal_store(v, g);
 #else
-  *p = v;
+  *g = v;
 #endif
 }
 
@@ -74,15 +81,15 @@ template <> struct Codec<ST_F32> {
   static __device__ __forceinline__ S enc(C v, C, C) { return v; }
 };
 // FP16 deviation: stored h = fp16((f - base) 2^s); 2^s and 2^-s are exact.
-// enc rounds to nearest.  enc_sr rounds stochastically: r holds 13 random
-// bits, added to the 13 FP32 mantissa bits that FP16 drops before
-// truncating, so the value rounds up with probability equal to its distance
-// from the lower FP16 neighbour (unbiased).  Round-to-nearest applied to a
-// nearly steady state rounds the same values the same way every step, and
-// increments below half an FP16 ulp (a weak body force, a slow viscous
-// correction) are lost every time; the stochastic form keeps them on
-// average.  Values below FP16's normal range (|h| < 2^-14) and near its top
-// round to nearest.
+// enc rounds to nearest.  enc_sr rounds stochastically with gfx950's
+// v_cvt_sr_f16_f32: the top 13 bits of the random word r are added below
+// the 10 mantissa bits FP16 keeps, then the rest is truncated, so a value
+// rounds up with probability equal to its distance from the lower FP16
+// neighbour (unbiased).  Round-to-nearest applied to a nearly steady state
+// rounds the same values the same way every step, and increments below
+// half an FP16 ulp (a weak body force, a slow viscous correction) are lost
+// every time; the stochastic form keeps them on average.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 template <> struct Codec<ST_F16> {
   using S = _Float16;
   using C = float;
@@ -93,20 +100,16 @@ template <> struct Codec<ST_F16> {
     return static_cast<_Float16>((v - base) * scale);
   }
   static __device__ __forceinline__ S enc_sr(C v, C base, C scale, unsigned r) {
-    float x = (v - base) * scale;
-    const unsigned u = __float_as_uint(x);
-    unsigned mag = u & 0x7fffffffu;
-    if (mag >= 0x38800000u && mag < 0x477fe000u) {  // [2^-14, 65504)
-      mag = (mag + (r & 0x1fffu)) & ~0x1fffu;
-      x = __uint_as_float((u & 0x80000000u) | mag);  // exactly an FP16 value
-    }
-    return static_cast<_Float16>(x);
+    const half2_t zero = {(_Float16)0.0f, (_Float16)0.0f};
+    const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(zero, (v - base) * scale, r, false);
+    return h[0];
   }
 };
 
-// Counter-based random bits for the FP16 dither: a hash of (node, time
-// level), then one mixing step per population.  Deterministic, so a lattice
-// gives the same bits alone or in a batch, in either memory pattern.
+// Counter-based random words for the FP16 dither: one hash of (node, time
+// level) per node, then a Weyl sequence over the populations (marginally
+// uniform top bits at one add each).  Deterministic, so a lattice gives the
+// same bits alone or in a batch, in either memory pattern.
 __device__ __forceinline__ unsigned node_hash(unsigned n, unsigned t) {
   unsigned x = (n * 0x9E3779B1u) ^ (t * 0x85EBCA77u + 0x165667B1u);
   x ^= x >> 16;
@@ -117,11 +120,7 @@ __device__ __forceinline__ unsigned node_hash(unsigned n, unsigned t) {
   return x;
 }
 __device__ __forceinline__ unsigned pop_bits(unsigned h, int a) {
-  unsigned x = h ^ (0x9E3779B9u * (unsigned)(a + 1));
-  x *= 0x85EBCA6Bu;
-  x ^= x >> 13;
-  x *= 0xC2B2AE35u;
-  return x >> 19;  // 13 bits
+  return h + 0x9E3779B9u * (unsigned)(a + 1);
 }
 
 // Encode a post-collision value: FP16 with the step's rounding mode, the
@@ -283,7 +282,7 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
 }
 
 // ---- one node, one step ------------------------------------------------------
-template <int Q, int ST, int MODE, bool FORCED, bool GEN>
+template <int Q, int ST, int MODE, bool FORCED, bool GEN, bool BGK = false>
 __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::C>& A, int x, int y,
                                           int z) {
   using CD = Codec<ST>;
@@ -298,66 +297,86 @@ __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::
   } else {
     read_node<Q, ST, 1, GEN>(A, static_cast<const S*>(A.f), n, x, y, z, f);
   }
-  Relax<C> r;
-#pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    r.sN[k] = A.sN[k];
-    r.hN[k] = A.hN[k];
-  }
   C F[3] = {A.F[0], A.F[1], A.F[2]};
-  collide<Q, C, FORCED>(f, r, F);
+  if constexpr (BGK) {
+    collide_bgk<Q, C, FORCED>(f, A.omega, A.hom, F);
+  } else {
+    Relax<C> r;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      r.sN[k] = A.sN[k];
+      r.hN[k] = A.hN[k];
+    }
+    collide<Q, C, FORCED>(f, r, F);
+  }
   write_node<Q, ST, MODE, GEN>(A, static_cast<S*>(MODE == MODE_AB ? A.g : A.f), n, x, y, z, f);
 }
 
 // Dispatch on whether this node's wavefront may touch a y or z boundary
 // (uniform for a wavefront inside one x-row).
-template <int Q, int ST, int MODE, bool FORCED>
+template <int Q, int ST, int MODE, bool FORCED, bool BGK = false>
 __device__ __forceinline__ void node_step_any(const LatticeArgs<typename Codec<ST>::C>& A, int x,
                                               int y, int z) {
   const bool inner = (y > 0) & (y < A.ny - 1) & (z > 0) & (z < A.nz - 1);
   if (inner)
-    node_step<Q, ST, MODE, FORCED, false>(A, x, y, z);
+    node_step<Q, ST, MODE, FORCED, false, BGK>(A, x, y, z);
   else
-    node_step<Q, ST, MODE, FORCED, true>(A, x, y, z);
+    node_step<Q, ST, MODE, FORCED, true, BGK>(A, x, y, z);
 }
 
-template <int Q, int ST, int MODE, bool FORCED>
+template <int Q, int ST, int MODE, bool FORCED, bool BGK = false>
 __global__ __launch_bounds__(256) void k_step(LatticeArgs<typename Codec<ST>::C> A) {
-  const int b = blockIdx.x;
-  const int bx = b % A.tiles_x;
-  const int r = b / A.tiles_x;
-  const int by = r % A.tiles_y;
-  const int z = r / A.tiles_y;
+  const unsigned b = blockIdx.x;
+  const unsigned r = fast_div(b, A.fd_tiles_x);
+  const int bx = (int)(b - r * (unsigned)A.tiles_x);
+  const unsigned zz = fast_div(r, A.fd_tiles_y);
+  const int by = (int)(r - zz * (unsigned)A.tiles_y);
+  const int z = (int)zz;
   const int x = bx * A.tx + (int)threadIdx.x;
   const int y = by * A.ty + (int)threadIdx.y;
   if (x >= A.nx || y >= A.ny) return;
-  node_step_any<Q, ST, MODE, FORCED>(A, x, y, z);
+  node_step_any<Q, ST, MODE, FORCED, BGK>(A, x, y, z);
 }
 
-template <int Q, int ST, int MODE, bool FORCED>
+template <int Q, int ST, int MODE, bool FORCED, bool BGK>
 static hipError_t step_launch(const void* args, hipStream_t s) {
   clear_stale_error();
   using C = typename Codec<ST>::C;
   const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
   const long long blocks = (long long)A.tiles_x * A.tiles_y * A.nz;
   dim3 block(A.tx, A.ty, 1);
-  hipLaunchKernelGGL((k_step<Q, ST, MODE, FORCED>), dim3((unsigned)blocks), block, 0, s, A);
+  hipLaunchKernelGGL((k_step<Q, ST, MODE, FORCED, BGK>), dim3((unsigned)blocks), block, 0, s, A);
   return hipGetLastError();
 }
 
-template <int Q, int ST>
+template <int Q, int ST, bool BGK = false>
 static hipError_t step_q_st(int mode, bool forced, const void* args, hipStream_t s) {
   clear_stale_error();
   switch (mode) {
     case MODE_AB:
-      return forced ? step_launch<Q, ST, MODE_AB, true>(args, s)
-                    : step_launch<Q, ST, MODE_AB, false>(args, s);
+      return forced ? step_launch<Q, ST, MODE_AB, true, BGK>(args, s)
+                    : step_launch<Q, ST, MODE_AB, false, BGK>(args, s);
     case MODE_AA_EVEN:
-      return forced ? step_launch<Q, ST, MODE_AA_EVEN, true>(args, s)
-                    : step_launch<Q, ST, MODE_AA_EVEN, false>(args, s);
+      return forced ? step_launch<Q, ST, MODE_AA_EVEN, true, BGK>(args, s)
+                    : step_launch<Q, ST, MODE_AA_EVEN, false, BGK>(args, s);
     case MODE_AA_ODD:
-      return forced ? step_launch<Q, ST, MODE_AA_ODD, true>(args, s)
-                    : step_launch<Q, ST, MODE_AA_ODD, false>(args, s);
+      return forced ? step_launch<Q, ST, MODE_AA_ODD, true, BGK>(args, s)
+                    : step_launch<Q, ST, MODE_AA_ODD, false, BGK>(args, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_bgk(int q, int storage, int mode, bool forced, const void* args,
+                           hipStream_t s) {
+  clear_stale_error();
+  if (q == 14) {
+    if (storage == ST_F64) return step_q_st<14, ST_F64, true>(mode, forced, args, s);
+    if (storage == ST_F32) return step_q_st<14, ST_F32, true>(mode, forced, args, s);
+    if (storage == ST_F16) return step_q_st<14, ST_F16, true>(mode, forced, args, s);
+  } else if (q == 18) {
+    if (storage == ST_F64) return step_q_st<18, ST_F64, true>(mode, forced, args, s);
+    if (storage == ST_F32) return step_q_st<18, ST_F32, true>(mode, forced, args, s);
+    if (storage == ST_F16) return step_q_st<18, ST_F16, true>(mode, forced, args, s);
   }
   return hipErrorInvalidValue;
 }
@@ -746,44 +765,15 @@ hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream
 }
 
 // ---- batched execution --------------------------------------------------------
-// One launch per time step over the tiles of every member.  A workgroup
-// finds its member by binary search over the members' first tile indices
-// (uniform scalar loads), then runs the same node update as k_step for that
-// member's q, storage, parity and force.  Per-member arithmetic does not
-// depend on the other members, so a member's result is the same alone and
-// in any mix.
-template <int Q, int ST, bool FORCED>
-__device__ __forceinline__ void batch_node(const BatchMember& m, int phase, const float* ftab,
-                                           int substep, int x, int y, int z) {
-  if (ST == ST_F32) {
-    LatticeArgs<float> A = m.a;
-    A.tstep = m.a.tstep + (unsigned)substep;
-    if (FORCED) {
-      const float* Fr = ftab + m.ftab_off + 3LL * substep;
-      A.F[0] = Fr[0];
-      A.F[1] = Fr[1];
-      A.F[2] = Fr[2];
-    }
-    if (phase == 0)
-      node_step_any<Q, ST_F32, MODE_AA_EVEN, FORCED>(A, x, y, z);
-    else
-      node_step_any<Q, ST_F32, MODE_AA_ODD, FORCED>(A, x, y, z);
-  } else {
-    LatticeArgs<float> A = m.a;
-    A.tstep = m.a.tstep + (unsigned)substep;
-    if (FORCED) {
-      const float* Fr = ftab + m.ftab_off + 3LL * substep;
-      A.F[0] = Fr[0];
-      A.F[1] = Fr[1];
-      A.F[2] = Fr[2];
-    }
-    if (phase == 0)
-      node_step_any<Q, ST_F16, MODE_AA_EVEN, FORCED>(A, x, y, z);
-    else
-      node_step_any<Q, ST_F16, MODE_AA_ODD, FORCED>(A, x, y, z);
-  }
-}
-
+// One launch per time step and (q, storage) class over the tiles of every
+// member of the class; the host aligns the members' AA parity (a member out
+// of step sits out one substep), so each launch runs exactly the node update
+// of k_step for one memory pattern.  A class with any forced member runs the
+// force path for all of them (with F = 0 it gives the same bits as the
+// unforced path).  A workgroup finds its member by binary search over the
+// members' first tile indices (uniform scalar loads).  Per-member
+// arithmetic does not depend on the other members, so a member's result is
+// the same alone and in any mix.
 __device__ __forceinline__ int find_member(const BatchMember* __restrict__ ms, int nm,
                                            long long tile) {
   int lo = 0, hi = nm - 1;
@@ -797,58 +787,80 @@ __device__ __forceinline__ int find_member(const BatchMember* __restrict__ ms, i
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_batch_step(const BatchMember* __restrict__ ms, int nm,
-                                                    const float* __restrict__ ftab, int substep) {
-  const long long tile = blockIdx.x;
+template <int Q, int ST, int MODE, bool FORCED>
+__global__ __launch_bounds__(256) void k_batch_grp(const BatchMember* __restrict__ ms, int nm,
+                                                   const float* __restrict__ ftab, int substep) {
+  const unsigned tile = blockIdx.x;
   const int mi = find_member(ms, nm, tile);
   const BatchMember& m = ms[mi];
-  if (substep >= m.steps) return;  // this member's budget is used up
-  const long long lt = tile - m.tile_begin;
-  if (lt >= m.ntiles) return;
-  const int tx = m.a.tx, ty = m.a.ty;
-  const int t = threadIdx.x;
-  if (t >= tx * ty) return;
-  const int bx = (int)(lt % m.a.tiles_x);
-  const long long r = lt / m.a.tiles_x;
-  const int by = (int)(r % m.a.tiles_y);
-  const int z = (int)(r / m.a.tiles_y);
-  const int x = bx * tx + t % tx;
-  const int y = by * ty + t / tx;
-  if (x >= m.a.nx || y >= m.a.ny) return;
-  const int phase = (m.phase0 + substep) & 1;
-  if (m.q == 14) {
-    if (m.storage == ST_F32) {
-      if (m.forced)
-        batch_node<14, ST_F32, true>(m, phase, ftab, substep, x, y, z);
-      else
-        batch_node<14, ST_F32, false>(m, phase, ftab, substep, x, y, z);
+  const int own = substep - m.skip;  // this member's own step within the call
+  if (own < 0 || own >= m.steps) return;
+  const unsigned lt = tile - (unsigned)m.tile_begin;
+  if (lt >= (unsigned)m.ntiles) return;
+  LatticeArgs<float> A = m.a;
+  const int tx = A.tx;
+  const unsigned t = threadIdx.x;
+  if (t >= (unsigned)(tx * A.ty)) return;
+  const unsigned r = fast_div(lt, A.fd_tiles_x);
+  const int bx = (int)(lt - r * (unsigned)A.tiles_x);
+  const unsigned zz = fast_div(r, A.fd_tiles_y);
+  const int by = (int)(r - zz * (unsigned)A.tiles_y);
+  const unsigned ly = fast_div(t, A.fd_tx);
+  const int x = bx * tx + (int)(t - ly * (unsigned)tx);
+  const int y = by * A.ty + (int)ly;
+  const int z = (int)zz;
+  if (x >= A.nx || y >= A.ny) return;
+  A.tstep += (unsigned)own;
+  if (FORCED) {
+    if (m.forced) {
+      const float* Fr = ftab + m.ftab_off + 3LL * own;
+      A.F[0] = Fr[0];
+      A.F[1] = Fr[1];
+      A.F[2] = Fr[2];
     } else {
-      if (m.forced)
-        batch_node<14, ST_F16, true>(m, phase, ftab, substep, x, y, z);
-      else
-        batch_node<14, ST_F16, false>(m, phase, ftab, substep, x, y, z);
-    }
-  } else {
-    if (m.storage == ST_F32) {
-      if (m.forced)
-        batch_node<18, ST_F32, true>(m, phase, ftab, substep, x, y, z);
-      else
-        batch_node<18, ST_F32, false>(m, phase, ftab, substep, x, y, z);
-    } else {
-      if (m.forced)
-        batch_node<18, ST_F16, true>(m, phase, ftab, substep, x, y, z);
-      else
-        batch_node<18, ST_F16, false>(m, phase, ftab, substep, x, y, z);
+      A.F[0] = A.F[1] = A.F[2] = 0.0f;
     }
   }
+  node_step_any<Q, ST, MODE, FORCED>(A, x, y, z);
 }
 
-hipError_t launch_batch_step(const BatchMember* ms, int nm, long long total_tiles,
-                             const float* ftab, int substep, hipStream_t s) {
+template <int Q, int ST, int MODE>
+static void batch_launch_f(bool forced, dim3 g, const BatchMember* ms, int nm, const float* ftab,
+                           int substep, hipStream_t s) {
+  if (forced)
+    hipLaunchKernelGGL((k_batch_grp<Q, ST, MODE, true>), g, dim3(256), 0, s, ms, nm, ftab, substep);
+  else
+    hipLaunchKernelGGL((k_batch_grp<Q, ST, MODE, false>), g, dim3(256), 0, s, ms, nm, ftab,
+                       substep);
+}
+
+template <int Q, int ST>
+static void batch_launch_m(int mode, bool forced, dim3 g, const BatchMember* ms, int nm,
+                           const float* ftab, int substep, hipStream_t s) {
+  if (mode == MODE_AA_EVEN)
+    batch_launch_f<Q, ST, MODE_AA_EVEN>(forced, g, ms, nm, ftab, substep, s);
+  else
+    batch_launch_f<Q, ST, MODE_AA_ODD>(forced, g, ms, nm, ftab, substep, s);
+}
+
+hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const BatchMember* ms,
+                              int nm, long long tiles, const float* ftab, int substep,
+                              hipStream_t s) {
   clear_stale_error();
-  if (nm <= 0 || total_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_step, dim3((unsigned)total_tiles), dim3(256), 0, s, ms, nm, ftab,
-                     substep);
+  if (nm <= 0 || tiles <= 0) return hipSuccess;
+  if (tiles >= (1LL << 30) || (mode != MODE_AA_EVEN && mode != MODE_AA_ODD))
+    return hipErrorInvalidValue;
+  const dim3 g((unsigned)tiles);
+  if (q == 14 && storage == ST_F32)
+    batch_launch_m<14, ST_F32>(mode, forced, g, ms, nm, ftab, substep, s);
+  else if (q == 14 && storage == ST_F16)
+    batch_launch_m<14, ST_F16>(mode, forced, g, ms, nm, ftab, substep, s);
+  else if (q == 18 && storage == ST_F32)
+    batch_launch_m<18, ST_F32>(mode, forced, g, ms, nm, ftab, substep, s);
+  else if (q == 18 && storage == ST_F16)
+    batch_launch_m<18, ST_F16>(mode, forced, g, ms, nm, ftab, substep, s);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

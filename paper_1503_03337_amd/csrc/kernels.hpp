@@ -12,6 +12,25 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2 };
 // AA_ODD: gather from the neighbours' opposite slots, collide, push.
 enum Mode { MODE_AB = 0, MODE_AA_EVEN = 1, MODE_AA_ODD = 2 };
 
+// Division by a fixed divisor d as a multiply and shift, for numerators
+// below 2^30: m = ceil(2^(32+l) / d), l = ceil(log2 d); the rounding error
+// n (m d - 2^(32+l)) / (d 2^(32+l)) stays below 1/(4d), so the floor is
+// exact.
+struct FastDiv {
+  unsigned long long m;
+  unsigned s;  // 32 + l
+  unsigned d;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  unsigned l = 0;
+  while ((1ull << l) < d) ++l;
+  const unsigned long long m = ((1ull << (32 + l)) + d - 1) / d;
+  return FastDiv{m, 32 + l, d};
+}
+__device__ __forceinline__ unsigned fast_div(unsigned n, const FastDiv& f) {
+  return (unsigned)(((unsigned long long)n * f.m) >> f.s);
+}
+
 // Everything a lattice kernel needs about one lattice, in compute type C.
 template <typename C> struct LatticeArgs {
   void* f;                 // populations (AB: the copy read this step)
@@ -28,11 +47,16 @@ template <typename C> struct LatticeArgs {
   C scale, inv_scale;      // FP16 2^s, 2^-s
   unsigned tstep;          // time level t of this step (FP16 rounding dither)
   int f16_sr;              // FP16 stores: 1 stochastic rounding, 0 nearest
+  FastDiv fd_tiles_x, fd_tiles_y, fd_tx;  // tile decoding without divisions
+  C omega, hom;            // LBGK collision: 1/tau, 1 - 1/(2 tau)
 };
 
 // Launches (all asynchronous on `stream`; return a hipError_t).
 hipError_t launch_step(int q, int storage, int mode, bool forced, const void* args,
                        size_t args_bytes, hipStream_t stream);
+// The same step with the LBGK collision (S = I/tau).
+hipError_t launch_step_bgk(int q, int storage, int mode, bool forced, const void* args,
+                           hipStream_t stream);
 // Decode population a of the current state (phase: 0 natural, 1 AA
 // swapped) into FP64 out[N].
 hipError_t launch_get_pop(int q, int storage, int phase, int a, const void* args, double* out,
@@ -63,17 +87,21 @@ hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream
 struct BatchMember {
   LatticeArgs<float> a;    // a.F unused: forces come from the F table
   int q, storage;
-  int phase0;              // AA parity at substep 0
-  int steps;               // substeps this member takes in this launch set
+  int phase0;              // AA parity at its first substep
+  int skip;                // first substep it takes part in (0 or 1: parity alignment)
+  int steps;               // substeps it takes, from substep `skip` on
   long long tile_begin;    // first global tile index of this member
   long long ntiles;
-  long long ftab_off;      // float offset of this member's F(t) rows (3 per substep)
+  long long ftab_off;      // float offset of this member's F(t) rows (3 per own step)
   int forced;
-  int pad_;
 };
-// One time step (substep s of the current quantum) of every member.
-hipError_t launch_batch_step(const BatchMember* members, int nmembers, long long total_tiles,
-                             const float* ftab, int substep, hipStream_t stream);
+// One time step (substep s of the current quantum) of every member of one
+// group: members[0..nmembers) share q, storage, the AA step kind `mode`
+// (MODE_AA_EVEN / MODE_AA_ODD at this substep) and `forced`; their
+// tile_begin counts from the group's first tile.
+hipError_t launch_batch_group(int q, int storage, int mode, bool forced,
+                              const BatchMember* members, int nmembers, long long group_tiles,
+                              const float* ftab, int substep, hipStream_t stream);
 // Monitor pass 1 of every member: partial sums into partial[3*blocks of
 // member]; member m writes at partial + 3*pofs[m].
 hipError_t launch_batch_monitor(const BatchMember* members, int nmembers, void* const* snaps,

@@ -308,6 +308,50 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
   }
 }
 
+// ---------------------------------------------------------------------------
+// Single-relaxation-time (LBGK) collision, the special case S = I/tau of the
+// MRT models (Sec. 3: Lambda-hat = I/tau gives the iD3Q15 LBGK model of
+// Sec. 2; Appendix B likewise for iD3Q19):
+//   f*_a = f_a - (f_a - f_eq_a)/tau + (1 - 1/(2 tau)) src_a,
+// f_eq from Eq. (edf), src_a = w_a [3 c.F + 9 (c.u)(c.F) - 3 u.F] the
+// velocity-space form of the moment force (no transform needed).
+// omega = 1/tau, hom = 1 - omega/2.
+// ---------------------------------------------------------------------------
+template <int Q, typename C, bool FORCED>
+__device__ __forceinline__ void collide_bgk(C (&f)[Q], C omega, C hom, const C (&F)[3]) {
+  using L = Lattice<Q>;
+  C P = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    P += f[a];
+    if (L::cx[a]) jx += L::cx[a] > 0 ? f[a] : -f[a];
+    if (L::cy[a]) jy += L::cy[a] > 0 ? f[a] : -f[a];
+    if (L::cz[a]) jz += L::cz[a] > 0 ? f[a] : -f[a];
+  }
+  C ux = jx, uy = jy, uz = jz;
+  if (FORCED) {
+    ux += C(0.5) * F[0];
+    uy += C(0.5) * F[1];
+    uz += C(0.5) * F[2];
+  }
+  const C usq = ux * ux + uy * uy + uz * uz;
+  // Eq. (hgl): p = (P - 3/2 w0 |u|^2) / (3 (1 - w0))
+  const C p = (P - C(1.5 * L::w0) * usq) * C(1.0 / (3.0 * (1.0 - L::w0)));
+  const C uF = FORCED ? ux * F[0] + uy * F[1] + uz * F[2] : C(0);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const C w = C(weight<Q>(a));
+    C cu = C(0), cF = C(0);
+    if (L::cx[a]) { cu += L::cx[a] > 0 ? ux : -ux; if (FORCED) cF += L::cx[a] > 0 ? F[0] : -F[0]; }
+    if (L::cy[a]) { cu += L::cy[a] > 0 ? uy : -uy; if (FORCED) cF += L::cy[a] > 0 ? F[1] : -F[1]; }
+    if (L::cz[a]) { cu += L::cz[a] > 0 ? uz : -uz; if (FORCED) cF += L::cz[a] > 0 ? F[2] : -F[2]; }
+    const C feq = w * (C(3) * p + C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq);
+    C fa = f[a] - omega * (f[a] - feq);
+    if (FORCED) fa += hom * (w * (C(3) * cF + C(9) * cu * cF - C(3) * uF));
+    f[a] = fa;
+  }
+}
+
 template <int Q, typename C, bool FORCED>
 __device__ __forceinline__ void collide(C (&f)[Q], const Relax<C>& r, const C (&F)[3]) {
   if constexpr (Q == 14)

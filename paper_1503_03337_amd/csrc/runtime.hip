@@ -63,6 +63,11 @@ std::string validate(int model, int nx, int ny, int nz, const double* s, const l
   if (sp->monitor_every < 0) return "monitor_every must be >= 0";
   if (sp->f16_rounding != LBM_ROUND_STOCHASTIC && sp->f16_rounding != LBM_ROUND_NEAREST)
     return "unknown f16_rounding";
+  if (sp->collision != LBM_MRT && sp->collision != LBM_BGK) return "unknown collision";
+  if (sp->collision == LBM_BGK && s) {
+    for (int k = 1; k < model; ++k)
+      if (s[k] != s[0]) return "LBM_BGK needs all relaxation rates equal (S = I/tau)";
+  }
   for (int d = 0; d < 3; ++d) {
     const int a = sp->face[2 * d], b = sp->face[2 * d + 1];
     if ((a != LBM_PERIODIC && a != LBM_WALL) || (b != LBM_PERIODIC && b != LBM_WALL))
@@ -187,6 +192,9 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
   A.ty = c.ty;
   A.tiles_x = (c.nx + c.tx - 1) / c.tx;
   A.tiles_y = (c.ny + c.ty - 1) / c.ty;
+  A.fd_tiles_x = make_fastdiv((unsigned)A.tiles_x);
+  A.fd_tiles_y = make_fastdiv((unsigned)A.tiles_y);
+  A.fd_tx = make_fastdiv((unsigned)A.tx);
   for (int k = 0; k < c.q; ++k) {
     A.sN[k] = (C)(c.s[k] / Nk[k]);
     A.hN[k] = (C)((1.0 - 0.5 * c.s[k]) / Nk[k]);
@@ -212,6 +220,8 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
   A.F[0] = A.F[1] = A.F[2] = 0;
   A.tstep = (unsigned)c.t;
   A.f16_sr = c.spec.f16_rounding == LBM_ROUND_STOCHASTIC ? 1 : 0;
+  A.omega = (C)c.s[0];
+  A.hom = (C)(1.0 - 0.5 * c.s[0]);
 }
 
 void refresh_args(lbm_ctx& c) {
@@ -337,6 +347,14 @@ int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz, const double* s
   c->stream = (hipStream_t)sp->stream;
   c->forced = has_force(c->spec);
   pick_tile(nx, ny, c->tx, c->ty);
+  {
+    const long long tiles = (long long)((nx + c->tx - 1) / c->tx) * ((ny + c->ty - 1) / c->ty) * nz;
+    if (tiles >= (1LL << 30)) {  // the kernels decode tile indices below 2^30
+      delete c;
+      g_create_err = "lattice needs too many workgroups (rows too short for its size)";
+      return LBM_EINVAL;
+    }
+  }
   (void)hipGetDevice(&c->device);
   const size_t need = lbm_footprint_bytes(model, nx, ny, nz, sp);
   c->footprint = need;
@@ -402,7 +420,10 @@ int lbm_step(lbm_ctx* c, long long n) {
     } else {
       mode = c->phase == 0 ? MODE_AA_EVEN : MODE_AA_ODD;
     }
-    HIPCHK(c, launch_step(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), 0, c->stream));
+    if (c->spec.collision == LBM_BGK)
+      HIPCHK(c, launch_step_bgk(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), c->stream));
+    else
+      HIPCHK(c, launch_step(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), 0, c->stream));
     if (c->spec.pattern == LBM_AB) {
       std::swap(c->popA, c->popB);
       c->a64.f = c->a32.f = c->popA;
@@ -579,7 +600,10 @@ const char* lbm_status_string(int s) {
 int lbm_destroy(lbm_ctx* c) {
   if (!c) return LBM_OK;
   if (c->batch) (void)lbm_batch_remove((lbm_batch*)c->batch, c);
-  (void)hipStreamSynchronize(c->stream);
+  // Wait only when device memory this library allocated is freed; a
+  // caller-owned buffer stays valid and its reuse is the caller's (stream-
+  // ordered) business, so queued work keeps running.
+  if ((c->own_buf && c->buf) || c->mon_buf) (void)hipStreamSynchronize(c->stream);
   if (c->own_buf && c->buf) (void)hipFree(c->buf);
   if (c->mon_buf) (void)hipFree(c->mon_buf);
   delete c;
@@ -679,6 +703,7 @@ int lbm_batch_add(lbm_batch* b, lbm_ctx* c, long long budget) {
   if (c->spec.storage == LBM_F64)
     return bfail(b, LBM_EINVAL, "batched members must store LBM_F32 or LBM_F16DEV");
   if (c->stream != b->stream) return bfail(b, LBM_EINVAL, "member stream differs from batch stream");
+  if (c->spec.collision != LBM_MRT) return bfail(b, LBM_EINVAL, "batched members use LBM_MRT");
   b->members.push_back(Member{c, budget, 0, 0});
   c->batch = b;
   return LBM_OK;
@@ -735,7 +760,23 @@ int lbm_batch_step(lbm_batch* b, long long n) {
     if (b->members[i].ctx->forced) ftab_rows += (size_t)k;
   }
   if (act.empty()) return LBM_OK;
+  // One specialised launch per (q, storage) class and step.  For n >= 2 the
+  // members run in step with the AA parity of the first active member (one
+  // out of step sits out the first substep of this call); for n == 1 the
+  // parity is part of the class instead.  Class bits: 4 odd parity (n == 1
+  // only), 2 q18, 1 FP16.
+  constexpr int NG = 8;
+  const bool align = n >= 2;
+  const int parity = b->members[act[0]].ctx->phase;
+  auto cls = [&](int i) {
+    const lbm_ctx* c = b->members[i].ctx;
+    return (align ? 0 : (c->phase ? 4 : 0)) + (c->q == 18 ? 2 : 0) +
+           (c->spec.storage == LBM_F32 ? 0 : 1);
+  };
+  std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return cls(x) < cls(y); });
   const int nm = (int)act.size();
+  int cls_off[NG] = {}, cls_cnt[NG] = {}, cls_forced[NG] = {};
+  long long cls_tiles[NG] = {}, cls_steps[NG] = {};
   // the pinned staging may still be read by the previous upload
   BHIP(b, hipEventSynchronize(b->staged));
   int rc = grow_host(b, b->h_members, b->h_members_cap, (size_t)nm);
@@ -743,11 +784,13 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   if (!rc) rc = grow_host(b, b->h_ftab, b->h_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
   if (!rc) rc = grow_dev(b, b->d_ftab, b->d_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
   if (rc) return rc;
-  long long tiles = 0;
   size_t frow = 0;
   for (int j = 0; j < nm; ++j) {
     Member& m = b->members[act[j]];
     lbm_ctx* c = m.ctx;
+    const int k_cls = cls(act[j]);
+    if (cls_cnt[k_cls]++ == 0) cls_off[k_cls] = j;
+    long long& tiles = cls_tiles[k_cls];
     BatchMember& bm = b->h_members[j];
     std::memset(&bm, 0, sizeof(bm));
     int tx = m.tx, ty = m.ty;
@@ -761,12 +804,15 @@ int lbm_batch_step(lbm_batch* b, long long n) {
     bm.q = c->q;
     bm.storage = c->spec.storage == LBM_F32 ? ST_F32 : ST_F16;
     bm.phase0 = c->phase;
-    const long long k = std::min(n, m.remaining);
+    bm.skip = (align && c->phase != parity) ? 1 : 0;
+    const long long k = std::min(n - bm.skip, m.remaining);
     bm.steps = (int)k;
     bm.tile_begin = tiles;
     bm.ntiles = (long long)bm.a.tiles_x * bm.a.tiles_y * c->nz;
     tiles += bm.ntiles;
+    cls_steps[k_cls] = std::max(cls_steps[k_cls], k + bm.skip);
     bm.forced = c->forced ? 1 : 0;
+    cls_forced[k_cls] |= bm.forced;
     bm.ftab_off = 3LL * (long long)frow;
     if (c->forced) {
       for (long long s = 0; s < k; ++s) {
@@ -777,18 +823,28 @@ int lbm_batch_step(lbm_batch* b, long long n) {
       frow += (size_t)k;
     }
   }
-  if (tiles >= (1LL << 31)) return bfail(b, LBM_EINVAL, "too many tiles in one batch");
+  for (int k = 0; k < NG; ++k)
+    if (cls_tiles[k] >= (1LL << 30)) return bfail(b, LBM_EINVAL, "too many tiles in one batch");
   BHIP(b, hipMemcpyAsync(b->d_members, b->h_members, nm * sizeof(BatchMember),
                          hipMemcpyHostToDevice, b->stream));
   if (frow)
     BHIP(b, hipMemcpyAsync(b->d_ftab, b->h_ftab, 3 * frow * sizeof(float), hipMemcpyHostToDevice,
                            b->stream));
   BHIP(b, hipEventRecord(b->staged, b->stream));
+  nmax = 0;
+  for (int k = 0; k < NG; ++k) nmax = std::max(nmax, cls_steps[k]);
   for (long long s = 0; s < nmax; ++s)
-    BHIP(b, launch_batch_step(b->d_members, nm, tiles, b->d_ftab, (int)s, b->stream));
+    for (int k = 0; k < NG; ++k) {
+      if (cls_cnt[k] == 0 || s >= cls_steps[k]) continue;
+      const int odd = (int)(((align ? parity : (k >> 2)) + s) & 1);
+      BHIP(b, launch_batch_group((k & 2) ? 18 : 14, (k & 1) ? ST_F16 : ST_F32,
+                                 odd ? MODE_AA_ODD : MODE_AA_EVEN, cls_forced[k] != 0,
+                                 b->d_members + cls_off[k], cls_cnt[k], cls_tiles[k], b->d_ftab,
+                                 (int)s, b->stream));
+    }
   for (int j = 0; j < nm; ++j) {
     Member& m = b->members[act[j]];
-    const long long k = std::min(n, m.remaining);
+    const long long k = std::min(n - ((align && m.ctx->phase != parity) ? 1 : 0), m.remaining);
     m.ctx->t += k;
     m.ctx->phase = (int)((m.ctx->phase + k) & 1);
     m.remaining -= k;

@@ -22,6 +22,7 @@ LIB_PATH = os.environ.get("LBM_LIB_PATH") or os.path.join(HERE, "liblbm.so")
 FACES = ("-x", "+x", "-y", "+y", "-z", "+z")
 STORAGE = {"f64": 0, "f32": 1, "f16dev": 2}
 ROUNDING = {"stochastic": 0, "nearest": 1}
+COLLISION = {"mrt": 0, "bgk": 1}
 PATTERN = {"ab": 0, "aa": 1}
 FACE_KIND = {"periodic": 0, "wall": 1}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
@@ -47,6 +48,7 @@ class Spec(C.Structure):
         ("pattern", C.c_int),
         ("f16_scale_log2", C.c_int),
         ("f16_rounding", C.c_int),
+        ("collision", C.c_int),
         ("monitor_every", C.c_int),
         ("stream", C.c_void_p),
         ("dev_buf", C.c_void_p),
@@ -132,7 +134,7 @@ def _dptr(a):
 
 def make_spec(faces=("wall",) * 6, wall_u=None, F0=(0, 0, 0), FA=(0, 0, 0), FT=0.0, p0=0.0,
               u0=(0, 0, 0), storage="f32", pattern="aa", f16_scale_log2=12,
-              f16_rounding="stochastic", monitor_every=0, stream=None):
+              f16_rounding="stochastic", collision="mrt", monitor_every=0, stream=None):
     sp = Spec()
     lib().lbm_spec_default(C.byref(sp))
     for k, fk in enumerate(faces):
@@ -157,6 +159,7 @@ def make_spec(faces=("wall",) * 6, wall_u=None, F0=(0, 0, 0), FA=(0, 0, 0), FT=0
     sp.pattern = PATTERN[pattern] if isinstance(pattern, str) else int(pattern)
     sp.f16_scale_log2 = int(f16_scale_log2)
     sp.f16_rounding = ROUNDING[f16_rounding] if isinstance(f16_rounding, str) else int(f16_rounding)
+    sp.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     sp.monitor_every = int(monitor_every)
     sp.stream = stream
     return sp

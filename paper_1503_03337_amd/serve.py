@@ -24,6 +24,7 @@ import numpy as np
 from . import autotune, inputs, lbm, params
 
 MONITOR_EVERY = 100   # residual lag (steps) for requests with a residual stop
+RESIDUAL_EVERY = 500  # a residual stop is checked when the request's t is a multiple
 DUCT_UMAX = 0.05      # centre-line speed of duct requests
 CAVITY_RE = 400.0     # cavity Reynolds number at lid speed 0.1
 DUCT_EFOLD = 1500.0   # slowest duct mode decays within this many steps
@@ -95,14 +96,15 @@ def serve_plain(trace, storage="f32", keep_fields=False):
         rec["admit"] = clock.now()
         lat = make_lattice(req, storage)
         if req.get("stop_residual"):
+            # the monitor runs every MONITOR_EVERY steps inside lbm_step;
+            # the stop is checked every RESIDUAL_EVERY steps (lag 100)
             done = 0
             while done < req["steps"]:
-                k = min(MONITOR_EVERY, req["steps"] - done)
+                k = min(RESIDUAL_EVERY, req["steps"] - done)
                 lat.step(k)
                 done += k
-                if done >= 2 * MONITOR_EVERY and done % MONITOR_EVERY == 0:
-                    if lat.residual() <= req["stop_residual"]:
-                        break
+                if done % RESIDUAL_EVERY == 0 and lat.residual() <= req["stop_residual"]:
+                    break
         else:
             lat.step(req["steps"])
         torch.cuda.current_stream().synchronize()
@@ -116,16 +118,36 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
                   keep_fields=False, tiles=None):
     """Continuous batching with admission by HBM footprint.
 
+    The loop keeps the device busy: quantum k+1 is queued before the host
+    waits for quantum k (at most two in flight).  Members whose step budget
+    runs out leave the batch as soon as their last quantum is queued (the
+    host knows budgets without asking the device) and are reported when that
+    quantum completes.  A member with a residual stop follows its own clock,
+    as in the plain server: a monitor snapshot at t = RESIDUAL_EVERY k - 100
+    and a check at t = RESIDUAL_EVERY k (lag 100), so its result does not
+    depend on the other members.  quantum must divide 100.
     tiles: optional {(q, edge bucket): (tx, ty)} from autotune.tune."""
+    assert MONITOR_EVERY % quantum == 0 and RESIDUAL_EVERY % quantum == 0
     import torch
     clock = Clock()
     pending = sorted(trace, key=lambda r: r["arrival"])
-    batch = lbm.Batch(torch.cuda.current_stream().cuda_stream)
-    active = []  # (record, lattice)
+    stream = torch.cuda.current_stream()
+    batch = lbm.Batch(stream.cuda_stream)
+    active = []     # (record, lattice) in the batch
+    draining = []   # (event, [(record, lattice)]) left the batch, last quantum in flight
+    inflight = []   # events of queued quanta, oldest first
     used = peak = 0
-    launches = 0
+    launches = quanta = 0
     out = []
-    while pending or active:
+
+    def retire(rec, lat):
+        nonlocal used
+        _finish(rec, clock, lat, keep_fields)
+        used -= rec.pop("_need")
+        lat.close()
+        out.append(rec)
+
+    while pending or active or draining:
         now = clock.now()
         while pending and pending[0]["arrival"] <= now:
             need = footprint(pending[0], storage)
@@ -147,30 +169,48 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
             used += need
             peak = max(peak, used)
             active.append((rec, lat))
-        if not active:
-            if pending:
-                time.sleep(max(0.0, min(0.001, pending[0]["arrival"] - clock.now())))
-            continue
-        batch.step(quantum)
-        launches += quantum
-        if any(r.get("stop_residual") for r, _ in active):
-            batch.monitor()  # synchronises
-        else:
-            torch.cuda.current_stream().synchronize()
-        keep = []
-        for rec, lat in active:
-            done = batch.remaining(lat) == 0
-            if not done and rec.get("stop_residual") and lat.time >= 2 * quantum:
-                done = lat.residual() <= rec["stop_residual"]
+        if active:
+            if len(inflight) >= 2:
+                inflight.pop(0).synchronize()
+            batch.step(quantum)
+            launches += quantum
+            quanta += 1
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            inflight.append(ev)
+            done = [(r, l) for r, l in active if batch.remaining(l) == 0]
+            for r, l in active:
+                if not r.get("stop_residual") or batch.remaining(l) == 0:
+                    continue
+                t = l.time
+                if t % RESIDUAL_EVERY == RESIDUAL_EVERY - MONITOR_EVERY:
+                    l.monitor()  # snapshot, queued
+                elif t % RESIDUAL_EVERY == 0:
+                    l.monitor()
+                    if l.residual() <= r["stop_residual"]:  # synchronises
+                        done.append((r, l))
+            for r, l in done:
+                batch.remove(l)
+            ids = {id(l) for _, l in done}
+            active = [(r, l) for r, l in active if id(l) not in ids]
             if done:
-                batch.remove(lat)
-                _finish(rec, clock, lat, keep_fields)
-                used -= rec.pop("_need")
-                lat.close()
-                out.append(rec)
+                draining.append((ev, done))
+        keep = []
+        for ev, lst in draining:
+            if ev.query():
+                for r, l in lst:
+                    retire(r, l)
             else:
-                keep.append((rec, lat))
-        active = keep
+                keep.append((ev, lst))
+        draining = keep
+        if not active:
+            if draining:
+                ev, lst = draining.pop(0)
+                ev.synchronize()
+                for r, l in lst:
+                    retire(r, l)
+            elif pending:
+                time.sleep(max(0.0, min(0.001, pending[0]["arrival"] - clock.now())))
     batch.close()
     return out, {"peak_bytes": peak, "budget_bytes": budget_bytes, "step_launches": launches}
 

@@ -97,3 +97,16 @@ def test_params_match_paper_rates():
     assert abs(s[8] - 1.25) < 1e-15
     from oracle import analytic
     assert abs(params.DUCT_UMAX_COEFF - analytic.duct_steady_umax_coeff()) < 1e-14
+
+
+def test_bgk_needs_equal_rates_without_device():
+    import numpy as np
+    from paper_1503_03337_amd import lbm
+    L = lbm.lib()
+    sp = lbm.make_spec(collision="bgk")
+    h = C.c_void_p()
+    s = np.full(18, 1.2)
+    s[4] = 1.0
+    assert L.lbm_create(C.byref(h), 18, 8, 8, 8, s.ctypes.data_as(C.POINTER(C.c_double)),
+                        C.byref(sp)) == -1
+    assert b"equal" in L.lbm_last_error(None)

@@ -176,3 +176,27 @@ def test_batch_rejects_unsupported_members():
     b.close()
     lat.close()
     lat2.close()
+
+
+def test_mixed_parity_single_steps_and_alignment():
+    """Members at different AA parities: single-step calls keep parity in the
+    launch class; multi-step calls let the out-of-step member sit out one
+    substep.  Either way every member equals its alone run."""
+    alone = {k: run_alone(k, 9, 700 + k) for k in (0, 1, 2, 3)}
+    lats = {k: build(k, 700 + k) for k in (0, 1, 2, 3)}
+    b = lbm.Batch(lats[0].stream)
+    b.add(lats[0], 9)
+    b.add(lats[1], 9)
+    b.step(1)             # 0 and 1 at odd parity
+    b.add(lats[2], 9)     # even parity
+    b.step(1)             # n == 1: both parities in one call
+    b.step(1)
+    b.add(lats[3], 9)     # even parity again, others mixed
+    b.step(4)             # aligned: out-of-step members skip a substep
+    b.step(100)
+    for k, lat in lats.items():
+        assert lat.time == 9, (k, lat.time)
+        assert np.array_equal(lat.get_f(), alone[k]), "member %d" % k
+    b.close()
+    for lat in lats.values():
+        lat.close()

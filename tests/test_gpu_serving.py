@@ -12,13 +12,16 @@ pytestmark = pytest.mark.gpu
 
 
 def small_trace():
+    """Eight requests; two carry a residual stop that triggers before their
+    budget (checked every 500 steps of their own clock)."""
     reqs = []
     rng = np.random.default_rng(5)
     for i in range(8):
+        res = i in (2, 5)
         reqs.append({"id": i, "arrival": 0.002 * i, "kind": "duct" if i % 2 else "cavity",
                      "edge": int(rng.integers(16, 41)), "q": 14 if i % 3 else 18,
-                     "steps": int(rng.integers(150, 450)),
-                     "stop_residual": 1e-3 if i in (2, 5) else None})
+                     "steps": 3000 if res else int(rng.integers(150, 450)),
+                     "stop_residual": 5e-3 if res else None})
     return reqs
 
 
@@ -39,6 +42,8 @@ def test_mix_equals_alone_and_budget_respected(storage):
         assert a["steps_done"] == m["steps_done"], req
         if req["stop_residual"] is None:
             assert m["steps_done"] == req["steps"]
+        else:  # stopped by the residual, on its own 500-step schedule
+            assert m["steps_done"] < req["steps"] and m["steps_done"] % 500 == 0
         assert np.array_equal(a["u"], m["u"]), req
 
 
