@@ -36,6 +36,9 @@
  *                          -2 w_a (c_a . u_w) / c_s^2 taken from the linear
  *                          term of Eq. (edf) (the paper itself uses
  *                          non-equilibrium extrapolation)
+ *   symmetry planes ...... Eq. (z05symmetry) (Sec. 4.3): du/dn = dv/dn =
+ *                          dp/dn = 0, w = 0 on the plane, imposed by
+ *                          specular reflection at a half-way plane
  *
  * Layout: f[a*N + n], n = x + nx*(y + ny*z), a = 0..q-1 in the paper's
  * order 1..q.  Everything is FP64.  Build: -O2 -ffp-contract=off.
@@ -148,7 +151,8 @@ static int make_lattice(int q, lattice* L) {
 typedef struct {
   int q, nx, ny, nz;
   double s[QMAX];        /* relaxation rates in the order of Eq. (moment) */
-  int face[6];           /* -x,+x,-y,+y,-z,+z: 0 periodic, 1 wall         */
+  int face[6];           /* -x,+x,-y,+y,-z,+z: 0 periodic, 1 wall,
+                            2 symmetry plane                              */
   double wall_u[6][3];   /* wall velocity of each wall face               */
   double F0[3], FA[3];   /* body force F(t) = F0 + FA cos(2 pi t / FT)    */
   double FT;             /* FT <= 0: constant force F0                    */
@@ -302,9 +306,24 @@ static int check_problem(const orc_problem* pr, lattice* L) {
   int d;
   if (make_lattice(pr->q, L)) return -1;
   if (pr->nx < 1 || pr->ny < 1 || pr->nz < 1) return -1;
+  for (d = 0; d < 6; ++d)
+    if (pr->face[d] < 0 || pr->face[d] > 2) return -1;
   for (d = 0; d < 3; ++d)
     if ((pr->face[2 * d] == 0) != (pr->face[2 * d + 1] == 0)) return -1;
   return 0;
+}
+
+/* Index of the velocity equal to c_a with the components flagged in
+ * flip[] negated. */
+static int mirror_of(const lattice* L, int a, const int flip[3]) {
+  int b, d;
+  for (b = 0; b < L->q; ++b) {
+    int same = 1;
+    for (d = 0; d < 3; ++d)
+      if (L->c[b][d] != (flip[d] ? -L->c[a][d] : L->c[a][d])) same = 0;
+    if (same) return b;
+  }
+  return -1;
 }
 
 /* ---- the lattice step ------------------------------------------------ */
@@ -314,7 +333,10 @@ static int check_problem(const orc_problem* pr, lattice* L) {
  * (periodic axes wrap) or, if x + c_a lies beyond a wall face, returns to x
  * as the opposite population with the moving-wall term.  A link leaving
  * through several wall faces takes the velocity of the z face it crosses,
- * else the y face, else the x face. */
+ * else the y face, else the x face.  A link that crosses symmetry planes
+ * and no wall is reflected specularly: the components normal to the planes
+ * it crosses are reversed, so it arrives at x + c_a with those coordinates
+ * left unchanged, as the population of the mirrored velocity. */
 static void step_impl(const orc_problem* pr, const lattice* L, long long t,
                       const double* fin, double* fout) {
   const int nx = pr->nx, ny = pr->ny, nz = pr->nz, q = L->q;
@@ -336,17 +358,30 @@ static void step_impl(const orc_problem* pr, const lattice* L, long long t,
         for (a = 0; a < q; ++a) {
           int dst[3] = {x + L->c[a][0], y + L->c[a][1], z + L->c[a][2]};
           int dim[3] = {nx, ny, nz};
-          int out[3] = {0, 0, 0}, outside = 0;
+          int own[3] = {x, y, z};
+          int out[3] = {0, 0, 0}, outside = 0, flip[3] = {0, 0, 0}, mirrored = 0;
           for (d = 0; d < 3; ++d) {
+            int face;
             if (dst[d] >= 0 && dst[d] < dim[d]) continue;
-            if (pr->face[2 * d] == 0) {
+            face = 2 * d + (dst[d] < 0 ? 0 : 1);
+            if (pr->face[face] == 0) {
               dst[d] = (dst[d] + dim[d]) % dim[d];
+            } else if (pr->face[face] == 2) {
+              flip[d] = 1;
+              mirrored = 1;
             } else {
               out[d] = (dst[d] < 0) ? -1 : 1;
               outside = 1;
             }
           }
-          if (!outside) {
+          if (!outside && mirrored) {
+            int b = mirror_of(L, a, flip);
+            size_t m;
+            for (d = 0; d < 3; ++d)
+              if (flip[d]) dst[d] = own[d];
+            m = (size_t)dst[0] + (size_t)nx * ((size_t)dst[1] + (size_t)ny * dst[2]);
+            fout[(size_t)b * N + m] = fs[a];
+          } else if (!outside) {
             size_t m = (size_t)dst[0] +
                        (size_t)nx * ((size_t)dst[1] + (size_t)ny * dst[2]);
             fout[(size_t)a * N + m] = fs[a];

@@ -106,14 +106,14 @@ def collide(q, s, f, F=(0.0, 0.0, 0.0)):
 
 def problem(q, nx, ny, nz, s, faces=("periodic",) * 6, wall_u=None,
             F0=(0.0, 0.0, 0.0), FA=(0.0, 0.0, 0.0), FT=0.0):
-    """faces: 6 entries 'periodic'/'wall' in the order -x,+x,-y,+y,-z,+z;
+    """faces: 6 entries 'periodic'/'wall'/'symmetry' in the order -x,+x,-y,+y,-z,+z;
     wall_u: dict face-name -> (ux,uy,uz) or a 6x3 array."""
     pr = Problem()
     pr.q, pr.nx, pr.ny, pr.nz = q, nx, ny, nz
     for k in range(q):
         pr.s[k] = float(s[k])
     for i, fk in enumerate(faces):
-        pr.face[i] = {"periodic": 0, "wall": 1, 0: 0, 1: 1}[fk]
+        pr.face[i] = {"periodic": 0, "wall": 1, "symmetry": 2, 0: 0, 1: 1, 2: 2}[fk]
     if wall_u is not None:
         if isinstance(wall_u, dict):
             for name, v in wall_u.items():

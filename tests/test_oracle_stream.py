@@ -12,6 +12,9 @@ from oracle import runner as R
 
 FACESETS = {
     "periodic": ("periodic",) * 6,
+    "halfcavity": ("wall", "wall", "wall", "wall", "wall", "symmetry"),
+    "symchannel": ("periodic", "periodic", "periodic", "periodic", "symmetry", "symmetry"),
+    "symmix": ("symmetry", "wall", "periodic", "periodic", "wall", "symmetry"),
     "duct": ("periodic", "periodic", "wall", "wall", "wall", "wall"),
     "cavity": ("wall",) * 6,
     "channel": ("periodic", "periodic", "periodic", "periodic", "wall", "wall"),
@@ -22,25 +25,36 @@ FACESETS = {
 def pull_permutation(q, dims, faces, f):
     """Streaming with identity collision written in pull form: the value
     arriving at node y in direction a comes from y - c_a (periodic axes
-    wrap), or, if y - c_a lies beyond a wall, is y's own opposite
-    population (no-slip walls)."""
+    wrap); if y - c_a lies beyond a wall it is y's own opposite population
+    (no-slip walls); if it lies beyond symmetry planes only, it is the
+    mirrored population of the node reached by moving along the planes only
+    (specular reflection)."""
     c = velocities(q)
     opp = [int(np.nonzero((c == -c[a]).all(axis=1))[0][0]) for a in range(q)]
     nx, ny, nz = dims
     out = np.empty_like(f)
     for a in range(q):
         for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
+            own = [x, y, z]
             src = [x - c[a, 0], y - c[a, 1], z - c[a, 2]]
-            wall = False
+            wall, flip = False, [False] * 3
             for d, n in enumerate(dims):
                 if 0 <= src[d] < n:
                     continue
-                if faces[2 * d] == "periodic":
+                kind = faces[2 * d + (0 if src[d] < 0 else 1)]
+                if kind == "periodic":
                     src[d] %= n
+                elif kind == "symmetry":
+                    flip[d] = True
+                    src[d] = own[d]
                 else:
                     wall = True
             if wall:
                 out[a, z, y, x] = f[opp[a], z, y, x]
+            elif any(flip):
+                m = np.array([-v if fl else v for v, fl in zip(c[a], flip)])
+                b = int(np.nonzero((c == m).all(axis=1))[0][0])
+                out[a, z, y, x] = f[b, src[2], src[1], src[0]]
             else:
                 out[a, z, y, x] = f[a, src[2], src[1], src[0]]
     return out
@@ -200,3 +214,42 @@ def test_momentum_grows_by_NF_per_step(q):
     g = R.run(pr, f, 0, 7)
     j1 = np.einsum("ad,azyx->d", c, g)
     assert np.max(np.abs(j1 - j0 - 7 * 60 * F)) < 1e-14 * np.abs(f).sum()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_symmetry_plane_reproduces_full_channel(q):
+    """Sec. 4.3 imposes Eq. (z05symmetry) on a mid-plane to compute half the
+    cavity.  A force-driven channel between walls at both z ends must equal
+    the half channel with a wall below and a symmetry plane above."""
+    m, g = 6, 1e-5
+    s = svec(q, 1.3)
+    full = R.problem(q, 3, 2, 2 * m, s, faces=FACESETS["channel"], F0=(g, 0, 0))
+    half = R.problem(q, 3, 2, m, s,
+                     faces=("periodic", "periodic", "periodic", "periodic", "wall", "symmetry"),
+                     F0=(g, 0, 0))
+    ff = R.run(full, R.init_eq(full), 0, 3000)
+    fh = R.run(half, R.init_eq(half), 0, 3000)
+    _, uf = R.macros(full, ff, 3000)
+    _, uh = R.macros(half, fh, 3000)
+    assert np.max(np.abs(uf[:, :m] - uh)) <= 1e-12 * np.max(np.abs(uf))
+    # the premise: the full channel is mirror-symmetric about its mid-plane
+    assert np.max(np.abs(uf[0] - uf[0, ::-1])) <= 1e-12 * np.max(np.abs(uf))
+    assert np.max(np.abs(uf[2] + uf[2, ::-1])) <= 1e-12 * np.max(np.abs(uf))
+
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_symmetry_plane_reproduces_full_cavity(q):
+    """Lid on +y moving along x: the cavity is mirror-symmetric in z, so its
+    lower half equals the half cavity with a symmetry plane on +z, at every
+    time level (transient included)."""
+    m = 4
+    s = svec(q, 1.5) + np.linspace(-0.02, 0.02, q)
+    lid = {"+y": (0.08, 0.0, 0.0)}
+    full = R.problem(q, 6, 5, 2 * m, s, faces=FACESETS["cavity"], wall_u=lid)
+    half = R.problem(q, 6, 5, m, s, faces=FACESETS["halfcavity"], wall_u=lid)
+    ff = R.run(full, R.init_eq(full), 0, 60)
+    fh = R.run(half, R.init_eq(half), 0, 60)
+    pf, uf = R.macros(full, ff, 60)
+    ph, uh = R.macros(half, fh, 60)
+    assert np.max(np.abs(uf[:, :m] - uh)) <= 1e-13 * np.max(np.abs(uf))
+    assert np.max(np.abs(pf[:m] - ph)) <= 1e-13 * max(np.max(np.abs(pf)), 1e-30)
