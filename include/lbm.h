@@ -67,7 +67,14 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2 } lbm_storage;
  * step (read and write a node's own slots) and a neighbour step. */
 typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
 
-typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_face_kind;
+/* Boundary kind of a lattice face.  LBM_SYMMETRY is the symmetry plane of
+ * Eq. (z05symmetry) (Sec. 4.3 computes half the cavity with it): a
+ * population leaving through it is reflected specularly half-way across
+ * the link, f_a'(x + c_a with the crossed normal components removed, t+1) =
+ * f*_a(x), where c_a' is c_a with those normal components negated.  A link
+ * crossing a wall and a symmetry plane at once bounces back at the wall.
+ * wall_u is ignored on periodic and symmetry faces. */
+typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_SYMMETRY = 2 } lbm_face_kind;
 
 /* Rounding of LBM_F16DEV stores made by a time step.  Stochastic (the
  * default): a value rounds up with probability equal to its distance from

@@ -137,52 +137,62 @@ __device__ __forceinline__ typename Codec<ST>::S enc_step(const LatticeArgs<type
 
 // ---- neighbour offsets -----------------------------------------------------
 // For each axis and direction (-1, +1): the linear-index delta of the
-// neighbour (wrapped on periodic axes) and whether a wall is crossed.
+// neighbour (wrapped on periodic axes, 0 across a symmetry plane) and
+// whether a wall or a symmetry plane is crossed.
 struct Nbr {
   int ox[2], oy[2], oz[2];
   bool wx[2], wy[2], wz[2];
+  bool sx[2], sy[2], sz[2];
 };
 
-__device__ __forceinline__ void axis_nbr(int c, int n, int per, int stride, int (&o)[2],
-                                         bool (&w)[2]) {
+__device__ __forceinline__ void axis_nbr(int c, int n, int per, bool sym_lo, bool sym_hi,
+                                         int stride, int (&o)[2], bool (&w)[2], bool (&s)[2]) {
   const bool lo = (c == 0), hi = (c == n - 1);
   o[0] = lo ? (per ? (n - 1) * stride : 0) : -stride;
   o[1] = hi ? (per ? -(n - 1) * stride : 0) : stride;
-  w[0] = lo && !per;
-  w[1] = hi && !per;
+  s[0] = lo && sym_lo;
+  s[1] = hi && sym_hi;
+  w[0] = lo && !per && !sym_lo;
+  w[1] = hi && !per && !sym_hi;
 }
 
-// GEN = false: the caller guarantees 0 < y < ny-1 and 0 < z < nz-1, so only
-// x needs boundary handling (per lane); GEN = true handles every axis.
+// GEN = false: the caller guarantees 0 < y < ny-1 and 0 < z < nz-1 and that
+// neither x face is a symmetry plane, so only x walls and wrap-around need
+// handling (per lane); GEN = true handles every axis and face kind.
 template <bool GEN, typename C>
 __device__ __forceinline__ Nbr make_nbr(const LatticeArgs<C>& A, int x, int y, int z) {
   Nbr b;
-  axis_nbr(x, A.nx, A.per_x, 1, b.ox, b.wx);
   if (GEN) {
-    axis_nbr(y, A.ny, A.per_y, A.nx, b.oy, b.wy);
-    axis_nbr(z, A.nz, A.per_z, A.nx * A.ny, b.oz, b.wz);
+    axis_nbr(x, A.nx, A.per_x, A.sym & 1, A.sym & 2, 1, b.ox, b.wx, b.sx);
+    axis_nbr(y, A.ny, A.per_y, A.sym & 4, A.sym & 8, A.nx, b.oy, b.wy, b.sy);
+    axis_nbr(z, A.nz, A.per_z, A.sym & 16, A.sym & 32, A.nx * A.ny, b.oz, b.wz, b.sz);
   } else {
+    axis_nbr(x, A.nx, A.per_x, false, false, 1, b.ox, b.wx, b.sx);
     b.oy[0] = -A.nx;
     b.oy[1] = A.nx;
     b.oz[0] = -A.nx * A.ny;
     b.oz[1] = A.nx * A.ny;
     b.wy[0] = b.wy[1] = b.wz[0] = b.wz[1] = false;
+    b.sy[0] = b.sy[1] = b.sz[0] = b.sz[1] = false;
   }
   return b;
 }
 
-// Link from this node along direction (cx,cy,cz): offset, wall flag and
-// the wall term of population `a` leaving through the crossed face (z face
-// first, then y, then x).
+// Link of population `a` from this node along its velocity (cx,cy,cz):
+// offset of the node it lands on, wall flag, the wall term of the crossed
+// wall face (z face first, then y, then x) and the slot it lands in (a, or
+// its mirror image when symmetry planes are crossed and no wall is).
 template <int Q, typename C>
 __device__ __forceinline__ void link(const Nbr& b, const LatticeArgs<C>& A, int a, int cx, int cy,
-                                     int cz, int& off, bool& wall, C& term) {
+                                     int cz, int& off, bool& wall, C& term, int& slot) {
   off = 0;
   wall = false;
   term = C(0);
+  bool fx = false, fy = false, fz = false;
   if (cx) {
     const int k = cx > 0;
     off += b.ox[k];
+    fx = b.sx[k];
     if (b.wx[k]) {
       wall = true;
       term = A.bb[a][0];
@@ -191,6 +201,7 @@ __device__ __forceinline__ void link(const Nbr& b, const LatticeArgs<C>& A, int 
   if (cy) {
     const int k = cy > 0;
     off += b.oy[k];
+    fy = b.sy[k];
     if (b.wy[k]) {
       wall = true;
       term = A.bb[a][1];
@@ -199,18 +210,25 @@ __device__ __forceinline__ void link(const Nbr& b, const LatticeArgs<C>& A, int 
   if (cz) {
     const int k = cz > 0;
     off += b.oz[k];
+    fz = b.sz[k];
     if (b.wz[k]) {
       wall = true;
       term = A.bb[a][2];
     }
   }
+  const int lo = fy ? (fx ? mirror<Q>(a, 3) : mirror<Q>(a, 2)) : (fx ? mirror<Q>(a, 1) : a);
+  const int hi = fy ? (fx ? mirror<Q>(a, 7) : mirror<Q>(a, 6))
+                    : (fx ? mirror<Q>(a, 5) : mirror<Q>(a, 4));
+  slot = fz ? hi : lo;
 }
 
 // ---- reading the populations of node n ------------------------------------
 // PHASE 0: natural layout (AB, AA even).  PHASE 1: AA swapped layout after
 // an even step: f_a(x) = A[abar][x - c_a], or, when x - c_a is a wall,
 // A[a][x], where the even step already stored the bounced-back value
-// f*_abar(x) - 6 w_abar (c_abar . u_w).
+// f*_abar(x) - 6 w_abar (c_abar . u_w).  When x - c_a lies beyond symmetry
+// planes only, the source node keeps x's coordinates along their normals and
+// the slot is the mirror image of abar.
 template <int Q, int ST, int PHASE, bool GEN, bool NT = false>
 __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::C>& A,
                                           const typename Codec<ST>::S* src, unsigned n, int x,
@@ -228,11 +246,11 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int o = L::opp[a];
-      int off;
+      int off, slot;
       bool wall;
       C term;
-      link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term);
-      const long long idx = wall ? (a * st + n) : (o * st + (long long)(n + off));
+      link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term, slot);
+      const long long idx = wall ? (a * st + n) : (slot * st + (long long)(n + off));
       f[a] = CD::dec(pop_load<NT>(src + idx), A.base[a], A.inv_scale);
     }
   }
@@ -242,7 +260,9 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
 // MODE_AA_EVEN: f*_a into slot abar of the same node, minus the wall term
 // when x + c_a is a wall (so the value stored is the bounced-back
 // population, rounded once, as in the push patterns).  Otherwise push to
-// x + c_a (or bounce back into slot abar of this node across a wall).
+// x + c_a (or bounce back into slot abar of this node across a wall, or,
+// across symmetry planes only, into the mirror slot of the node reached by
+// moving along the planes).
 template <int Q, int ST, int MODE, bool GEN>
 __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>::C>& A,
                                            typename Codec<ST>::S* dst, unsigned n, int x, int y,
@@ -258,10 +278,10 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int o = L::opp[a];
-      int off;
+      int off, slot;
       bool wall;
       C term;
-      link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term);
+      link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
       pop_store(dst + o * st + n, enc_step<ST>(A, wall ? f[a] - term : f[a], o, h, a));
     }
   } else {
@@ -269,14 +289,15 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int o = L::opp[a];
-      int off;
+      int off, slot;
       bool wall;
       C term;
-      link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term);
+      link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
+      // (a mirror image has a's weight, hence a's FP16 base)
       if (wall)
         pop_store(dst + o * st + n, enc_step<ST>(A, f[a] - term, o, h, a));
       else
-        pop_store(dst + a * st + (long long)(n + off), enc_step<ST>(A, f[a], a, h, a));
+        pop_store(dst + slot * st + (long long)(n + off), enc_step<ST>(A, f[a], a, h, a));
     }
   }
 }
@@ -313,11 +334,13 @@ __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::
 }
 
 // Dispatch on whether this node's wavefront may touch a y or z boundary
-// (uniform for a wavefront inside one x-row).
+// (uniform for a wavefront inside one x-row); lattices with a symmetry plane
+// on an x face take the general path everywhere.
 template <int Q, int ST, int MODE, bool FORCED, bool BGK = false>
 __device__ __forceinline__ void node_step_any(const LatticeArgs<typename Codec<ST>::C>& A, int x,
                                               int y, int z) {
-  const bool inner = (y > 0) & (y < A.ny - 1) & (z > 0) & (z < A.nz - 1);
+  const bool inner =
+      (y > 0) & (y < A.ny - 1) & (z > 0) & (z < A.nz - 1) & ((A.sym & 3) == 0);
   if (inner)
     node_step<Q, ST, MODE, FORCED, false, BGK>(A, x, y, z);
   else

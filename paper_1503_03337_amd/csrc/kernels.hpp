@@ -38,6 +38,8 @@ template <typename C> struct LatticeArgs {
   long long stride;        // elements between population arrays (= N)
   int nx, ny, nz;
   int per_x, per_y, per_z; // periodic axes
+  int sym;                 // bit f set: face f (-x,+x,-y,+y,-z,+z) is a
+                           // symmetry plane (specular reflection)
   int tx, ty, tiles_x, tiles_y;  // x-y tile of one workgroup
   C sN[18], hN[18];        // s_k/N_k, (1 - s_k/2)/N_k
   C bb[18][3];             // 6 w_a (c_a . u_w) for link a leaving through

@@ -49,6 +49,20 @@ __host__ __device__ constexpr double weight(int a) {
              : Lattice<Q>::w_diag;
 }
 
+// Index of the velocity equal to c_a with the components of the axes in
+// `mask` (bit 0 x, bit 1 y, bit 2 z) negated: the population a specular
+// reflection off planes normal to those axes turns a into.
+template <int Q>
+__host__ __device__ constexpr int mirror(int a, int mask) {
+  using L = Lattice<Q>;
+  const int mx = (mask & 1) ? -L::cx[a] : L::cx[a];
+  const int my = (mask & 2) ? -L::cy[a] : L::cy[a];
+  const int mz = (mask & 4) ? -L::cz[a] : L::cz[a];
+  for (int b = 0; b < Q; ++b)
+    if (L::cx[b] == mx && L::cy[b] == my && L::cz[b] == mz) return b;
+  return -1;
+}
+
 // Per-moment relaxation coefficients, pre-divided by the row norms:
 //   sN_k = s_k / N_k,   hN_k = (1 - s_k/2) / N_k,
 // so that d_k = D_k / N_k = sN_k (m_k - meq_k) - hN_k mF_k.

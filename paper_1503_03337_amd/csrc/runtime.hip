@@ -70,8 +70,8 @@ std::string validate(int model, int nx, int ny, int nz, const double* s, const l
   }
   for (int d = 0; d < 3; ++d) {
     const int a = sp->face[2 * d], b = sp->face[2 * d + 1];
-    if ((a != LBM_PERIODIC && a != LBM_WALL) || (b != LBM_PERIODIC && b != LBM_WALL))
-      return "face kind must be LBM_PERIODIC or LBM_WALL";
+    if (a < LBM_PERIODIC || a > LBM_SYMMETRY || b < LBM_PERIODIC || b > LBM_SYMMETRY)
+      return "face kind must be LBM_PERIODIC, LBM_WALL or LBM_SYMMETRY";
     if ((a == LBM_PERIODIC) != (b == LBM_PERIODIC)) return "periodic faces must come in pairs";
   }
   for (int f = 0; f < 6; ++f) {
@@ -188,6 +188,9 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
   A.per_x = c.spec.face[0] == LBM_PERIODIC;
   A.per_y = c.spec.face[2] == LBM_PERIODIC;
   A.per_z = c.spec.face[4] == LBM_PERIODIC;
+  A.sym = 0;
+  for (int f = 0; f < 6; ++f)
+    if (c.spec.face[f] == LBM_SYMMETRY) A.sym |= 1 << f;
   A.tx = c.tx;
   A.ty = c.ty;
   A.tiles_x = (c.nx + c.tx - 1) / c.tx;

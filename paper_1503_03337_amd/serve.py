@@ -7,11 +7,18 @@ budget or a stop at a velocity residual) arrive over time.  Two servers:
            single-lattice kernel (lbm_step)
   batched  continuous batching: arrived requests are admitted, in arrival
            order, while their HBM footprint (lbm_footprint_bytes) fits the
-           budget; all admitted requests advance together, one kernel launch
-           per time step (lbm_batch_step), in quanta of Q steps; between
-           quanta finished requests retire (freeing their memory) and
-           waiting ones are admitted, so new work overlaps running work on
-           the device.  Storage FP32 or FP16 deviations.
+           budget and the admitted lattices hold fewer nodes than it takes
+           to fill the GPU (max_active_nodes); all admitted requests advance
+           together, one kernel launch per time step and lattice class
+           (lbm_batch_step), in quanta of Q steps; between quanta finished
+           requests retire (freeing their memory) and waiting ones are
+           admitted, so new work overlaps running work on the device.
+           Storage FP32 or FP16 deviations.
+
+The node cap keeps the batch from turning into processor sharing: once the
+admitted lattices saturate HBM bandwidth, admitting more only slows every
+admitted request down, so large requests run one after another (as in the
+plain server) while small ones, which cannot fill the GPU alone, share it.
 
 Latency is arrival -> finish.  Aggregate throughput is the node updates of
 all requests over the time from the first arrival to the last finish.
@@ -28,6 +35,9 @@ RESIDUAL_EVERY = 500  # a residual stop is checked when the request's t is a mul
 DUCT_UMAX = 0.05      # centre-line speed of duct requests
 CAVITY_RE = 400.0     # cavity Reynolds number at lid speed 0.1
 DUCT_EFOLD = 1500.0   # slowest duct mode decays within this many steps
+# A lattice of 2^21 nodes (128^3) runs the single-lattice kernel at its full
+# bandwidth on MI355X; batches are filled up to that many nodes.
+SATURATION_NODES = 1 << 21
 
 
 def duct_nu(edge):
@@ -115,7 +125,7 @@ def serve_plain(trace, storage="f32", keep_fields=False):
 
 
 def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
-                  keep_fields=False, tiles=None):
+                  keep_fields=False, tiles=None, max_active_nodes=SATURATION_NODES):
     """Continuous batching with admission by HBM footprint.
 
     The loop keeps the device busy: quantum k+1 is queued before the host
@@ -126,7 +136,10 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
     as in the plain server: a monitor snapshot at t = RESIDUAL_EVERY k - 100
     and a check at t = RESIDUAL_EVERY k (lag 100), so its result does not
     depend on the other members.  quantum must divide 100.
-    tiles: optional {(q, edge bucket): (tx, ty)} from autotune.tune."""
+    tiles: optional {(q, edge bucket): (tx, ty)} from autotune.tune.
+    max_active_nodes: admission stops while the admitted lattices hold this
+    many nodes (a request is always admitted into an empty batch); None
+    admits whatever fits the memory budget."""
     assert MONITOR_EVERY % quantum == 0 and RESIDUAL_EVERY % quantum == 0
     import torch
     clock = Clock()
@@ -137,6 +150,7 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
     draining = []   # (event, [(record, lattice)]) left the batch, last quantum in flight
     inflight = []   # events of queued quanta, oldest first
     used = peak = 0
+    active_nodes = 0
     launches = quanta = 0
     out = []
 
@@ -156,6 +170,10 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
                                  (pending[0]["id"], need, budget_bytes))
             if used + need > budget_bytes:
                 break  # wait for memory: admitted in arrival order
+            nodes = pending[0]["edge"] ** 3
+            if (max_active_nodes is not None and active
+                    and active_nodes + nodes > max_active_nodes):
+                break  # the GPU is full: wait in arrival order
             req = pending.pop(0)
             rec = dict(req)
             rec["admit"] = clock.now()
@@ -167,6 +185,7 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
                     batch.set_tile(lat, *t)
             rec["_need"] = need
             used += need
+            active_nodes += nodes
             peak = max(peak, used)
             active.append((rec, lat))
         if active:
@@ -191,6 +210,7 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
                         done.append((r, l))
             for r, l in done:
                 batch.remove(l)
+                active_nodes -= r["edge"] ** 3
             ids = {id(l) for _, l in done}
             active = [(r, l) for r, l in active if id(l) not in ids]
             if done:

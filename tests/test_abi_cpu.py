@@ -59,6 +59,8 @@ def test_footprint_without_device():
     dict(model=15), dict(nx=0), dict(faces=("periodic", "wall") + ("wall",) * 4),
     dict(wall_u={"+z": (0.3, 0, 0)}), dict(storage=7), dict(pattern=5),
     dict(storage="f16dev", f16_scale_log2=30), dict(monitor_every=-1),
+    dict(faces=("periodic", "symmetry") + ("wall",) * 4), dict(faces=(3,) + ("wall",) * 5),
+    dict(faces=("wall",) * 5 + (-1,)),
 ])
 def test_footprint_rejects_invalid(bad):
     from paper_1503_03337_amd import lbm
@@ -110,3 +112,10 @@ def test_bgk_needs_equal_rates_without_device():
     assert L.lbm_create(C.byref(h), 18, 8, 8, 8, s.ctypes.data_as(C.POINTER(C.c_double)),
                         C.byref(sp)) == -1
     assert b"equal" in L.lbm_last_error(None)
+
+
+def test_footprint_accepts_symmetry_faces():
+    from paper_1503_03337_amd import lbm
+    for faces in (("wall",) * 5 + ("symmetry",),
+                  ("symmetry", "symmetry", "periodic", "periodic", "wall", "symmetry")):
+        assert lbm.footprint_bytes(18, 8, 8, 8, faces=faces) > 0

@@ -22,6 +22,11 @@ MEMBERS = [
     (14, (13, 29, 7), "f16dev", ("wall",) * 6, {"+z": (0.05, 0.02, 0)}, (0, 0, 0), (0, 0, 0),
      0.0),
     (18, (300, 4, 3), "f32", ("periodic",) * 6, None, (1e-5, 1e-5, 0), (0, 0, 0), 0.0),
+    # symmetry planes (Sec. 4.3 half cavity; an x-face plane)
+    (18, (21, 15, 8), "f32", ("wall",) * 5 + ("symmetry",), {"+y": (0.1, 0, 0)}, (0, 0, 0),
+     (0, 0, 0), 0.0),
+    (14, (17, 12, 10), "f16dev", ("symmetry", "wall", "periodic", "periodic", "wall", "symmetry"),
+     {"+x": (0, 0.04, 0.02)}, (1e-5, 0, 0), (0, 0, 0), 0.0),
 ]
 
 
@@ -52,7 +57,7 @@ def run_alone(k, nsteps, seed, via_batch=True):
 
 
 def test_alone_equals_mix_bit_exact():
-    budgets = [7, 5, 9, 6, 8]
+    budgets = [7, 5, 9, 6, 8, 10, 4]
     alone = [run_alone(k, budgets[k], 100 + k) for k in range(len(MEMBERS))]
     lats = [build(k, 100 + k) for k in range(len(MEMBERS))]
     b = lbm.Batch(lats[0].stream)

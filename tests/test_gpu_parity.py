@@ -18,7 +18,7 @@ checkpoint/restore.
 import numpy as np
 import pytest
 
-from helpers import svec
+from helpers import svec, velocities
 from oracle import runner as R
 from paper_1503_03337_amd import inputs
 from paper_1503_03337_amd import lbm
@@ -30,6 +30,9 @@ FACESETS = {
     "duct": ("periodic", "periodic", "wall", "wall", "wall", "wall"),
     "cavity": ("wall",) * 6,
     "xwalls": ("wall", "wall", "periodic", "periodic", "periodic", "periodic"),
+    "halfcavity": ("wall", "wall", "wall", "wall", "wall", "symmetry"),
+    "symmix": ("symmetry", "wall", "periodic", "periodic", "wall", "symmetry"),
+    "symchannel": ("periodic", "periodic", "symmetry", "symmetry", "wall", "wall"),
 }
 SETUPS = {
     # name: (faces, wall_u, F0, FA, FT)
@@ -38,6 +41,11 @@ SETUPS = {
     "cavity_lid": ("cavity", {"+z": (0.1, 0.0, 0.0), "-x": (0.0, 0.03, 0.0)}, (0, 0, 0),
                    (0, 0, 0), 0.0),
     "xwalls_force": ("xwalls", {"-x": (0.0, 0.05, 0.0)}, (0, 2e-5, 0), (0, 0, 0), 0.0),
+    # Sec. 4.3: half cavity, symmetry plane on +z, lid on +y
+    "halfcavity_lid": ("halfcavity", {"+y": (0.1, 0.0, 0.0), "-x": (0.0, 0.0, 0.03)},
+                       (0, 0, 0), (0, 0, 0), 0.0),
+    "symmix_force": ("symmix", {"+x": (0.0, 0.04, 0.02), "-z": (0.03, 0.0, 0.0)},
+                     (1e-5, 2e-5, -1e-5), (0, 0, 0), 0.0),
 }
 DIMS = [(37, 19, 11), (300, 3, 4)]
 
@@ -166,21 +174,39 @@ def test_fp16_stochastic_rounding_is_unbiased():
 
 
 def pull_permutation(q, dims, faces, f):
-    """Pure streaming written in pull form (test-side, independent)."""
-    c, _, opp, _, _, _ = R.lattice(q)
+    """Zero-rate step in pull form, vectorised: population a at y comes from
+    y - c_a (wrapped on periodic axes); beyond a wall it is y's own opposite
+    population; beyond symmetry planes only it is the population mirrored
+    in those planes, taken from the node reached along the planes."""
+    c = velocities(q)
+    opp = [int(np.nonzero((c == -c[a]).all(axis=1))[0][0]) for a in range(q)]
     nx, ny, nz = dims
     out = np.empty_like(f)
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    own = [x, y, z]
     for a in range(q):
         src = [x - c[a, 0], y - c[a, 1], z - c[a, 2]]
         wall = np.zeros(x.shape, bool)
+        mask = np.zeros(x.shape, int)
         for d, n in enumerate(dims):
-            if faces[2 * d] == "periodic":
+            lo, hi = src[d] < 0, src[d] >= n
+            kinds = (faces[2 * d], faces[2 * d + 1])
+            if kinds[0] == "periodic":
                 src[d] = src[d] % n
-            else:
-                wall |= (src[d] < 0) | (src[d] >= n)
-                src[d] = np.clip(src[d], 0, n - 1)
-        moved = f[a][src[2], src[1], src[0]]
+                continue
+            for side, kind in ((lo, kinds[0]), (hi, kinds[1])):
+                if kind == "wall":
+                    wall |= side
+                else:  # symmetry plane
+                    mask |= np.where(side, 1 << d, 0)
+                    src[d] = np.where(side, own[d], src[d])
+            src[d] = np.clip(src[d], 0, n - 1)
+        moved = np.empty(x.shape)
+        for m in range(8):
+            cm = c[a] * np.array([-1 if m >> d & 1 else 1 for d in range(3)])
+            b = int(np.nonzero((c == cm).all(axis=1))[0][0])
+            sel = mask == m
+            moved[sel] = f[b][src[2][sel], src[1][sel], src[0][sel]]
         out[a] = np.where(wall, f[opp[a]], moved)
     return out
 

@@ -109,3 +109,27 @@ def test_pulsatile_duct_q18_64x64x128(eta):
     # second-order bounce-back error at a = 32 (the T/2 and T samples sit
     # near a flow reversal, where the relative norm is largest)
     assert max(e[1] for e in out["f64"]) <= 0.05
+
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_half_cavity_with_symmetry_plane_fp32(q):
+    """Sec. 4.3 computes the cavity on half the grid with a symmetry plane at
+    mid-depth.  The lid moves along x on +y, so the cube is mirror-symmetric
+    in z: the half cavity (symmetry plane on +z) must reproduce the lower
+    half of the full cavity, at half the memory."""
+    n, steps = 48, 600
+    s = svec(q, s_nu_of(0.1 * n / 400.0))
+    lid = {"+y": (0.1, 0.0, 0.0)}
+    full = lbm.Lattice(q, n, n, n, s, faces=("wall",) * 6, wall_u=lid, storage="f32")
+    half = lbm.Lattice(q, n, n, n // 2, s, faces=("wall",) * 5 + ("symmetry",), wall_u=lid,
+                       storage="f32")
+    full.step(steps)
+    half.step(steps)
+    _, uf = full.macros()
+    _, uh = half.macros()
+    full.close()
+    half.close()
+    low = uf[:, : n // 2]
+    err = np.max(np.abs(low - uh)) / np.max(np.abs(low))
+    print("half cavity q=%d: max|u_half - u_full|/max|u| %.2e" % (q, err))
+    assert err <= 1e-5
