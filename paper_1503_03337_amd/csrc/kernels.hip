@@ -797,12 +797,14 @@ hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream
 // members' first tile indices (uniform scalar loads).  Per-member
 // arithmetic does not depend on the other members, so a member's result is
 // the same alone and in any mix.
+// Members of a small launch class: one tile per workgroup, the member found
+// by binary search over the members' first tiles.
 __device__ __forceinline__ int find_member(const BatchMember* __restrict__ ms, int nm,
-                                           long long tile) {
+                                           unsigned tile) {
   int lo = 0, hi = nm - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (ms[mid].tile_begin <= tile)
+    if (ms[mid].tile_begin <= (long long)tile)
       lo = mid;
     else
       hi = mid - 1;
@@ -810,16 +812,10 @@ __device__ __forceinline__ int find_member(const BatchMember* __restrict__ ms, i
   return lo;
 }
 
+// Per-node work of a batched step once the member and its tile are known.
 template <int Q, int ST, int MODE, bool FORCED>
-__global__ __launch_bounds__(256) void k_batch_grp(const BatchMember* __restrict__ ms, int nm,
-                                                   const float* __restrict__ ftab, int substep) {
-  const unsigned tile = blockIdx.x;
-  const int mi = find_member(ms, nm, tile);
-  const BatchMember& m = ms[mi];
-  const int own = substep - m.skip;  // this member's own step within the call
-  if (own < 0 || own >= m.steps) return;
-  const unsigned lt = tile - (unsigned)m.tile_begin;
-  if (lt >= (unsigned)m.ntiles) return;
+__device__ __forceinline__ void batch_tile(const BatchMember& m, const float* __restrict__ ftab,
+                                           int own, unsigned lt) {
   LatticeArgs<float> A = m.a;
   const int tx = A.tx;
   const unsigned t = threadIdx.x;
@@ -831,7 +827,6 @@ __global__ __launch_bounds__(256) void k_batch_grp(const BatchMember* __restrict
   const unsigned ly = fast_div(t, A.fd_tx);
   const int x = bx * tx + (int)(t - ly * (unsigned)tx);
   const int y = by * A.ty + (int)ly;
-  const int z = (int)zz;
   if (x >= A.nx || y >= A.ny) return;
   A.tstep += (unsigned)own;
   if (FORCED) {
@@ -844,44 +839,71 @@ __global__ __launch_bounds__(256) void k_batch_grp(const BatchMember* __restrict
       A.F[0] = A.F[1] = A.F[2] = 0.0f;
     }
   }
-  node_step_any<Q, ST, MODE, FORCED>(A, x, y, z);
+  node_step_any<Q, ST, MODE, FORCED>(A, x, y, (int)zz);
 }
 
-template <int Q, int ST, int MODE>
-static void batch_launch_f(bool forced, dim3 g, const BatchMember* ms, int nm, const float* ftab,
-                           int substep, hipStream_t s) {
-  if (forced)
-    hipLaunchKernelGGL((k_batch_grp<Q, ST, MODE, true>), g, dim3(256), 0, s, ms, nm, ftab, substep);
+template <int Q, int ST, int MODE, bool FORCED>
+__global__ __launch_bounds__(256) void k_batch_grp(const BatchMember* __restrict__ ms, int nm,
+                                                   const float* __restrict__ ftab, int substep) {
+  const unsigned tile = blockIdx.x;
+  const BatchMember& m = ms[find_member(ms, nm, tile)];
+  const int own = substep - m.skip;  // this member's own step within the call
+  if (own < 0 || own >= m.steps) return;
+  const unsigned lt = tile - (unsigned)m.tile_begin;
+  if (lt >= (unsigned)m.ntiles) return;
+  batch_tile<Q, ST, MODE, FORCED>(m, ftab, own, lt);
+}
+
+// Members of a large launch class: workgroup b runs the kBatchChunk tiles
+// of chunks[b] one after the other (fewer, longer-lived workgroups).
+template <int Q, int ST, int MODE, bool FORCED>
+__global__ __launch_bounds__(256) void k_batch_chunk(const BatchMember* __restrict__ ms,
+                                                     const BatchChunk* __restrict__ chunks,
+                                                     const float* __restrict__ ftab,
+                                                     int substep) {
+  const BatchChunk ch = chunks[blockIdx.x];
+  const BatchMember& m = ms[ch.member];
+  const int own = substep - m.skip;
+  if (own < 0 || own >= m.steps) return;
+  const unsigned end = (unsigned)min((long long)ch.tile + kBatchChunk, m.ntiles);
+  for (unsigned lt = (unsigned)ch.tile; lt < end; ++lt)
+    batch_tile<Q, ST, MODE, FORCED>(m, ftab, own, lt);
+}
+
+template <int Q, int ST, int MODE, bool FORCED>
+static void batch_launch_k(const BatchLaunch& L, hipStream_t s) {
+  if (L.chunks)
+    hipLaunchKernelGGL((k_batch_chunk<Q, ST, MODE, FORCED>), dim3((unsigned)L.nblocks), dim3(256),
+                       0, s, L.members, L.chunks, L.ftab, L.substep);
   else
-    hipLaunchKernelGGL((k_batch_grp<Q, ST, MODE, false>), g, dim3(256), 0, s, ms, nm, ftab,
-                       substep);
+    hipLaunchKernelGGL((k_batch_grp<Q, ST, MODE, FORCED>), dim3((unsigned)L.nblocks), dim3(256), 0,
+                       s, L.members, L.nmembers, L.ftab, L.substep);
 }
 
 template <int Q, int ST>
-static void batch_launch_m(int mode, bool forced, dim3 g, const BatchMember* ms, int nm,
-                           const float* ftab, int substep, hipStream_t s) {
+static void batch_launch_m(int mode, bool forced, const BatchLaunch& L, hipStream_t s) {
   if (mode == MODE_AA_EVEN)
-    batch_launch_f<Q, ST, MODE_AA_EVEN>(forced, g, ms, nm, ftab, substep, s);
+    forced ? batch_launch_k<Q, ST, MODE_AA_EVEN, true>(L, s)
+           : batch_launch_k<Q, ST, MODE_AA_EVEN, false>(L, s);
   else
-    batch_launch_f<Q, ST, MODE_AA_ODD>(forced, g, ms, nm, ftab, substep, s);
+    forced ? batch_launch_k<Q, ST, MODE_AA_ODD, true>(L, s)
+           : batch_launch_k<Q, ST, MODE_AA_ODD, false>(L, s);
 }
 
-hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const BatchMember* ms,
-                              int nm, long long tiles, const float* ftab, int substep,
+hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const BatchLaunch& L,
                               hipStream_t s) {
   clear_stale_error();
-  if (nm <= 0 || tiles <= 0) return hipSuccess;
-  if (tiles >= (1LL << 30) || (mode != MODE_AA_EVEN && mode != MODE_AA_ODD))
+  if (L.nblocks <= 0 || L.nmembers <= 0) return hipSuccess;
+  if (L.nblocks >= (1LL << 31) || (mode != MODE_AA_EVEN && mode != MODE_AA_ODD))
     return hipErrorInvalidValue;
-  const dim3 g((unsigned)tiles);
   if (q == 14 && storage == ST_F32)
-    batch_launch_m<14, ST_F32>(mode, forced, g, ms, nm, ftab, substep, s);
+    batch_launch_m<14, ST_F32>(mode, forced, L, s);
   else if (q == 14 && storage == ST_F16)
-    batch_launch_m<14, ST_F16>(mode, forced, g, ms, nm, ftab, substep, s);
+    batch_launch_m<14, ST_F16>(mode, forced, L, s);
   else if (q == 18 && storage == ST_F32)
-    batch_launch_m<18, ST_F32>(mode, forced, g, ms, nm, ftab, substep, s);
+    batch_launch_m<18, ST_F32>(mode, forced, L, s);
   else if (q == 18 && storage == ST_F16)
-    batch_launch_m<18, ST_F16>(mode, forced, g, ms, nm, ftab, substep, s);
+    batch_launch_m<18, ST_F16>(mode, forced, L, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -97,13 +97,32 @@ struct BatchMember {
   long long ftab_off;      // float offset of this member's F(t) rows (3 per own step)
   int forced;
 };
-// One time step (substep s of the current quantum) of every member of one
-// group: members[0..nmembers) share q, storage, the AA step kind `mode`
-// (MODE_AA_EVEN / MODE_AA_ODD at this substep) and `forced`; their
-// tile_begin counts from the group's first tile.
-hipError_t launch_batch_group(int q, int storage, int mode, bool forced,
-                              const BatchMember* members, int nmembers, long long group_tiles,
-                              const float* ftab, int substep, hipStream_t stream);
+// Tiles of one member run one after the other by one workgroup of a large
+// batched launch.
+constexpr int kBatchChunk = 2;
+
+// A chunk of a large batched launch: member index (into that launch's
+// member array) and the member's first tile of the chunk; the chunk covers
+// tiles [tile, min(tile + kBatchChunk, ntiles)) of that member.
+struct BatchChunk {
+  int member;
+  int tile;
+};
+
+// One launch of a batched time step: members[0..nmembers) share q, storage,
+// the AA step kind and `forced`.  chunks == NULL: one tile per workgroup,
+// nblocks = the members' tiles, each member's tile_begin counting from 0 at
+// members[0].  Otherwise workgroup b runs chunks[b] (nblocks chunks).
+struct BatchLaunch {
+  const BatchMember* members;
+  int nmembers;
+  const BatchChunk* chunks;
+  long long nblocks;
+  const float* ftab;
+  int substep;
+};
+hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const BatchLaunch& L,
+                              hipStream_t stream);
 // Monitor pass 1 of every member: partial sums into partial[3*blocks of
 // member]; member m writes at partial + 3*pofs[m].
 hipError_t launch_batch_monitor(const BatchMember* members, int nmembers, void* const* snaps,

@@ -631,6 +631,11 @@ struct Member {
 };
 }  // namespace
 
+// Launch classes of at least this many tiles (2^22 nodes at 256 nodes a
+// tile, 64 tiles per compute unit) run kBatchChunk tiles per workgroup;
+// smaller ones one tile per workgroup, so that they keep enough workgroups.
+constexpr long long kBatchChunkMinTiles = 16384;
+
 struct lbm_batch {
   hipStream_t stream = nullptr;
   std::vector<Member> members;
@@ -638,11 +643,15 @@ struct lbm_batch {
   // device staging (grown on demand)
   BatchMember* d_members = nullptr;
   size_t d_members_cap = 0;
+  BatchChunk* d_chunks = nullptr;
+  size_t d_chunks_cap = 0;
   float* d_ftab = nullptr;
   size_t d_ftab_cap = 0;
   // pinned host staging + the event that says it may be reused
   BatchMember* h_members = nullptr;
   size_t h_members_cap = 0;
+  BatchChunk* h_chunks = nullptr;
+  size_t h_chunks_cap = 0;
   float* h_ftab = nullptr;
   size_t h_ftab_cap = 0;
   hipEvent_t staged = nullptr;
@@ -780,19 +789,42 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   const int nm = (int)act.size();
   int cls_off[NG] = {}, cls_cnt[NG] = {}, cls_forced[NG] = {};
   long long cls_tiles[NG] = {}, cls_steps[NG] = {};
+  // chunks (large classes only): a member's tiles in runs of kBatchChunk,
+  // grouped by class
+  auto member_tiles = [&](int i) {
+    const lbm_ctx* c = b->members[i].ctx;
+    int tx = b->members[i].tx, ty = b->members[i].ty;
+    if (tx == 0) pick_tile(c->nx, c->ny, tx, ty);
+    return (long long)((c->nx + tx - 1) / tx) * ((c->ny + ty - 1) / ty) * c->nz;
+  };
+  long long all_tiles[NG] = {};
+  for (int i : act) all_tiles[cls(i)] += member_tiles(i);
+  bool cls_big[NG];
+  for (int k = 0; k < NG; ++k) cls_big[k] = all_tiles[k] >= kBatchChunkMinTiles;
+  long long nchunks = 0;
+  for (int i : act)
+    if (cls_big[cls(i)]) nchunks += (member_tiles(i) + kBatchChunk - 1) / kBatchChunk;
+  if (nchunks >= (1LL << 31)) return bfail(b, LBM_EINVAL, "too many tiles in one batch");
+  long long cls_chunk_off[NG] = {}, cls_chunks[NG] = {};
   // the pinned staging may still be read by the previous upload
   BHIP(b, hipEventSynchronize(b->staged));
   int rc = grow_host(b, b->h_members, b->h_members_cap, (size_t)nm);
   if (!rc) rc = grow_dev(b, b->d_members, b->d_members_cap, (size_t)nm);
+  if (!rc) rc = grow_host(b, b->h_chunks, b->h_chunks_cap, std::max<long long>(nchunks, 1));
+  if (!rc) rc = grow_dev(b, b->d_chunks, b->d_chunks_cap, std::max<long long>(nchunks, 1));
   if (!rc) rc = grow_host(b, b->h_ftab, b->h_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
   if (!rc) rc = grow_dev(b, b->d_ftab, b->d_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
   if (rc) return rc;
   size_t frow = 0;
+  long long chunk = 0;
   for (int j = 0; j < nm; ++j) {
     Member& m = b->members[act[j]];
     lbm_ctx* c = m.ctx;
     const int k_cls = cls(act[j]);
-    if (cls_cnt[k_cls]++ == 0) cls_off[k_cls] = j;
+    if (cls_cnt[k_cls]++ == 0) {
+      cls_off[k_cls] = j;
+      cls_chunk_off[k_cls] = chunk;
+    }
     long long& tiles = cls_tiles[k_cls];
     BatchMember& bm = b->h_members[j];
     std::memset(&bm, 0, sizeof(bm));
@@ -813,6 +845,13 @@ int lbm_batch_step(lbm_batch* b, long long n) {
     bm.tile_begin = tiles;
     bm.ntiles = (long long)bm.a.tiles_x * bm.a.tiles_y * c->nz;
     tiles += bm.ntiles;
+    if (cls_big[k_cls])
+      for (long long t0 = 0; t0 < bm.ntiles; t0 += kBatchChunk) {
+        b->h_chunks[chunk].member = j - cls_off[k_cls];
+        b->h_chunks[chunk].tile = (int)t0;
+        ++chunk;
+        ++cls_chunks[k_cls];
+      }
     cls_steps[k_cls] = std::max(cls_steps[k_cls], k + bm.skip);
     bm.forced = c->forced ? 1 : 0;
     cls_forced[k_cls] |= bm.forced;
@@ -828,8 +867,12 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   }
   for (int k = 0; k < NG; ++k)
     if (cls_tiles[k] >= (1LL << 30)) return bfail(b, LBM_EINVAL, "too many tiles in one batch");
+  if (chunk != nchunks) return bfail(b, LBM_EINVAL, "internal: chunk count mismatch");
   BHIP(b, hipMemcpyAsync(b->d_members, b->h_members, nm * sizeof(BatchMember),
                          hipMemcpyHostToDevice, b->stream));
+  if (nchunks)
+    BHIP(b, hipMemcpyAsync(b->d_chunks, b->h_chunks, nchunks * sizeof(BatchChunk),
+                           hipMemcpyHostToDevice, b->stream));
   if (frow)
     BHIP(b, hipMemcpyAsync(b->d_ftab, b->h_ftab, 3 * frow * sizeof(float), hipMemcpyHostToDevice,
                            b->stream));
@@ -840,10 +883,16 @@ int lbm_batch_step(lbm_batch* b, long long n) {
     for (int k = 0; k < NG; ++k) {
       if (cls_cnt[k] == 0 || s >= cls_steps[k]) continue;
       const int odd = (int)(((align ? parity : (k >> 2)) + s) & 1);
+      BatchLaunch L;
+      L.members = b->d_members + cls_off[k];
+      L.nmembers = cls_cnt[k];
+      L.chunks = cls_big[k] ? b->d_chunks + cls_chunk_off[k] : nullptr;
+      L.nblocks = cls_big[k] ? cls_chunks[k] : cls_tiles[k];
+      L.ftab = b->d_ftab;
+      L.substep = (int)s;
       BHIP(b, launch_batch_group((k & 2) ? 18 : 14, (k & 1) ? ST_F16 : ST_F32,
-                                 odd ? MODE_AA_ODD : MODE_AA_EVEN, cls_forced[k] != 0,
-                                 b->d_members + cls_off[k], cls_cnt[k], cls_tiles[k], b->d_ftab,
-                                 (int)s, b->stream));
+                                 odd ? MODE_AA_ODD : MODE_AA_EVEN, cls_forced[k] != 0, L,
+                                 b->stream));
     }
   for (int j = 0; j < nm; ++j) {
     Member& m = b->members[act[j]];
@@ -943,9 +992,11 @@ int lbm_batch_destroy(lbm_batch* b) {
   (void)hipStreamSynchronize(b->stream);
   for (auto& m : b->members) m.ctx->batch = nullptr;
   if (b->d_members) (void)hipFree(b->d_members);
+  if (b->d_chunks) (void)hipFree(b->d_chunks);
   if (b->d_ftab) (void)hipFree(b->d_ftab);
   if (b->d_mon) (void)hipFree(b->d_mon);
   if (b->h_members) (void)hipHostFree(b->h_members);
+  if (b->h_chunks) (void)hipHostFree(b->h_chunks);
   if (b->h_ftab) (void)hipHostFree(b->h_ftab);
   if (b->staged) (void)hipEventDestroy(b->staged);
   delete b;

@@ -205,3 +205,38 @@ def test_mixed_parity_single_steps_and_alignment():
     b.close()
     for lat in lats.values():
         lat.close()
+
+
+def test_large_class_two_tiles_per_workgroup_bit_exact():
+    """A class of at least 16384 tiles runs two tiles per workgroup; each
+    member still equals its alone run (one tile per workgroup) bit for bit,
+    including a ragged last chunk (odd tile counts)."""
+    q, steps = 18, 5
+    dims = [(112, 112, 112), (112, 113, 113), (112, 112, 111)]  # 6272 + 6441 + 6216 tiles
+    s = svec(q, 1.6) + np.linspace(-0.02, 0.02, q)
+
+    def make(k):
+        nx, ny, nz = dims[k]
+        lat = lbm.Lattice(q, nx, ny, nz, s, faces=("wall",) * 6, wall_u={"+z": (0.1, 0, 0)},
+                          storage="f32", pattern="aa")
+        lat.init_fields(np.zeros((nz, ny, nx)), inputs.random_fields(nx, ny, nz, seed=800 + k)[1])
+        return lat
+
+    alone = []
+    for k in range(3):
+        lat = make(k)
+        b = lbm.Batch(lat.stream)
+        b.add(lat, steps)
+        b.step(steps)
+        b.close()
+        alone.append(lat.macros()[1])
+        lat.close()
+    lats = [make(k) for k in range(3)]
+    b = lbm.Batch(lats[0].stream)
+    for lat in lats:
+        b.add(lat, steps)
+    b.step(steps)
+    b.close()
+    for k, lat in enumerate(lats):
+        assert np.array_equal(lat.macros()[1], alone[k]), k
+        lat.close()
