@@ -7,15 +7,15 @@ budget or a stop at a velocity residual) arrive over time.  Two servers:
            single-lattice kernel (lbm_step)
   batched  continuous batching: arrived requests are admitted, in arrival
            order, while their HBM footprint (lbm_footprint_bytes) fits the
-           budget and the admitted lattices hold fewer nodes than it takes
-           to fill the GPU (max_active_nodes); all admitted requests advance
-           together, one kernel launch per time step and lattice class
+           budget and the admitted lattices move fewer bytes per step than
+           it takes to fill the GPU (max_active_bytes); all admitted requests
+           advance together, one kernel launch per time step and lattice class
            (lbm_batch_step), in quanta of Q steps; between quanta finished
            requests retire (freeing their memory) and waiting ones are
            admitted, so new work overlaps running work on the device.
            Storage FP32 or FP16 deviations.
 
-The node cap keeps the batch from turning into processor sharing: once the
+The traffic cap keeps the batch from turning into processor sharing: once the
 admitted lattices saturate HBM bandwidth, admitting more only slows every
 admitted request down, so large requests run one after another (as in the
 plain server) while small ones, which cannot fill the GPU alone, share it.
@@ -35,9 +35,16 @@ RESIDUAL_EVERY = 500  # a residual stop is checked when the request's t is a mul
 DUCT_UMAX = 0.05      # centre-line speed of duct requests
 CAVITY_RE = 400.0     # cavity Reynolds number at lid speed 0.1
 DUCT_EFOLD = 1500.0   # slowest duct mode decays within this many steps
-# A lattice of 2^21 nodes (128^3) runs the single-lattice kernel at its full
-# bandwidth on MI355X; batches are filled up to that many nodes.
-SATURATION_NODES = 1 << 21
+# A D3Q18 FP32 lattice of 2^21 nodes (128^3, 2 x 18 x 4 B moved per node
+# and step) runs the single-lattice kernel at full bandwidth on MI355X;
+# batches are filled up to that many bytes moved per step.
+SATURATION_BYTES = (1 << 21) * 144
+STORAGE_BYTES = {"f32": 4, "f16dev": 2, "f64": 8}
+
+
+def step_bytes(req, storage):
+    """Bytes a request's lattice moves per time step: 2 q b per node."""
+    return 2 * req["q"] * STORAGE_BYTES[storage] * req["edge"] ** 3
 
 
 def duct_nu(edge):
@@ -125,7 +132,7 @@ def serve_plain(trace, storage="f32", keep_fields=False):
 
 
 def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
-                  keep_fields=False, tiles=None, max_active_nodes=SATURATION_NODES):
+                  keep_fields=False, tiles=None, max_active_bytes=SATURATION_BYTES):
     """Continuous batching with admission by HBM footprint.
 
     The loop keeps the device busy: quantum k+1 is queued before the host
@@ -137,9 +144,9 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
     and a check at t = RESIDUAL_EVERY k (lag 100), so its result does not
     depend on the other members.  quantum must divide 100.
     tiles: optional {(q, edge bucket): (tx, ty)} from autotune.tune.
-    max_active_nodes: admission stops while the admitted lattices hold this
-    many nodes (a request is always admitted into an empty batch); None
-    admits whatever fits the memory budget."""
+    max_active_bytes: admission stops while the admitted lattices move this
+    many bytes per step (a request is always admitted into an empty batch);
+    None admits whatever fits the memory budget."""
     assert MONITOR_EVERY % quantum == 0 and RESIDUAL_EVERY % quantum == 0
     import torch
     clock = Clock()
@@ -150,7 +157,7 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
     draining = []   # (event, [(record, lattice)]) left the batch, last quantum in flight
     inflight = []   # events of queued quanta, oldest first
     used = peak = 0
-    active_nodes = 0
+    active_bytes = 0
     launches = quanta = 0
     out = []
 
@@ -170,9 +177,9 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
                                  (pending[0]["id"], need, budget_bytes))
             if used + need > budget_bytes:
                 break  # wait for memory: admitted in arrival order
-            nodes = pending[0]["edge"] ** 3
-            if (max_active_nodes is not None and active
-                    and active_nodes + nodes > max_active_nodes):
+            moved = step_bytes(pending[0], storage)
+            if (max_active_bytes is not None and active
+                    and active_bytes + moved > max_active_bytes):
                 break  # the GPU is full: wait in arrival order
             req = pending.pop(0)
             rec = dict(req)
@@ -185,7 +192,7 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
                     batch.set_tile(lat, *t)
             rec["_need"] = need
             used += need
-            active_nodes += nodes
+            active_bytes += moved
             peak = max(peak, used)
             active.append((rec, lat))
         if active:
@@ -210,7 +217,7 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
                         done.append((r, l))
             for r, l in done:
                 batch.remove(l)
-                active_nodes -= r["edge"] ** 3
+                active_bytes -= step_bytes(r, storage)
             ids = {id(l) for _, l in done}
             active = [(r, l) for r, l in active if id(l) not in ids]
             if done:
