@@ -39,6 +39,13 @@
  *   symmetry planes ...... Eq. (z05symmetry) (Sec. 4.3): du/dn = dv/dn =
  *                          dp/dn = 0, w = 0 on the plane, imposed by
  *                          specular reflection at a half-way plane
+ *   non-equilibrium ...... the boundary scheme the paper applies throughout
+ *   extrapolation          Sec. 4 (Guo, Zheng & Shi): boundary nodes lie on
+ *                          the face; after streaming, each takes the
+ *                          equilibrium of its boundary values plus the
+ *                          non-equilibrium part of its inward neighbour;
+ *                          a velocity face fixes u and takes p from the
+ *                          neighbour, a pressure face (Eq. (bc)) the reverse
  *
  * Layout: f[a*N + n], n = x + nx*(y + ny*z), a = 0..q-1 in the paper's
  * order 1..q.  Everything is FP64.  Build: -O2 -ffp-contract=off.
@@ -152,10 +159,13 @@ typedef struct {
   int q, nx, ny, nz;
   double s[QMAX];        /* relaxation rates in the order of Eq. (moment) */
   int face[6];           /* -x,+x,-y,+y,-z,+z: 0 periodic, 1 wall,
-                            2 symmetry plane                              */
-  double wall_u[6][3];   /* wall velocity of each wall face               */
+                            2 symmetry plane, 3 velocity face and 4
+                            pressure face (non-equilibrium extrapolation) */
+  double wall_u[6][3];   /* velocity of each wall or velocity face        */
   double F0[3], FA[3];   /* body force F(t) = F0 + FA cos(2 pi t / FT)    */
-  double FT;             /* FT <= 0: constant force F0                    */
+  double FT;             /* FT <= 0: constant force F0 and face pressure  */
+  double face_p0[6];     /* pressure of a pressure face:                  */
+  double face_pA[6];     /*   p(t) = p0 + pA cos(2 pi t / FT)             */
 } orc_problem;
 
 /* ---- single-node pieces ---------------------------------------------- */
@@ -302,14 +312,25 @@ static void force_at(const orc_problem* pr, long long t, double F[3]) {
   for (d = 0; d < 3; ++d) F[d] = pr->F0[d] + (pr->FT > 0.0 ? pr->FA[d] * ph : 0.0);
 }
 
+static double face_pressure(const orc_problem* pr, int face, long long t) {
+  if (pr->FT > 0.0) return pr->face_p0[face] + pr->face_pA[face] * cos(2.0 * M_PI * (double)t / pr->FT);
+  return pr->face_p0[face];
+}
+
+static int is_nee(int kind) { return kind == 3 || kind == 4; }
+
 static int check_problem(const orc_problem* pr, lattice* L) {
   int d;
+  const int dim[3] = {pr->nx, pr->ny, pr->nz};
   if (make_lattice(pr->q, L)) return -1;
   if (pr->nx < 1 || pr->ny < 1 || pr->nz < 1) return -1;
   for (d = 0; d < 6; ++d)
-    if (pr->face[d] < 0 || pr->face[d] > 2) return -1;
-  for (d = 0; d < 3; ++d)
+    if (pr->face[d] < 0 || pr->face[d] > 4) return -1;
+  for (d = 0; d < 3; ++d) {
     if ((pr->face[2 * d] == 0) != (pr->face[2 * d + 1] == 0)) return -1;
+    /* a boundary node's inward neighbour must not lie on the opposite face */
+    if ((is_nee(pr->face[2 * d]) || is_nee(pr->face[2 * d + 1])) && dim[d] < 3) return -1;
+  }
   return 0;
 }
 
@@ -324,6 +345,56 @@ static int mirror_of(const lattice* L, int a, const int flip[3]) {
     if (same) return b;
   }
   return -1;
+}
+
+/* ---- non-equilibrium extrapolation ------------------------------------ */
+
+/* Boundary node x_b (on one to three velocity / pressure faces) after
+ * streaming to level t: its inward neighbour x_f = x_b + sum of the inward
+ * normals of those faces gives p_f, u_f and f_neq = f(x_f) - f_eq(p_f, u_f);
+ * then f(x_b) = f_eq(p_b, u_b) + f_neq, with u_b the velocity of a velocity
+ * face (else u_f) and p_b the pressure of a pressure face (else p_f).  When
+ * several faces of one kind meet at an edge or corner, the z face wins, then
+ * the y face, then the x face (as for wall velocities).  Returns 0 if x_b is
+ * on no such face. */
+static int nee_node(const orc_problem* pr, const lattice* L, long long t, int x, int y, int z,
+                    double* f) {
+  const int dim[3] = {pr->nx, pr->ny, pr->nz};
+  const int own[3] = {x, y, z};
+  const size_t N = (size_t)pr->nx * pr->ny * pr->nz;
+  int src[3] = {x, y, z}, d, a, on = 0, vface = -1, pface = -1;
+  double F[3], fn[QMAX], pf, uf[3], fe[QMAX], ub[3], pb;
+  for (d = 0; d < 3; ++d) {
+    int face = -1;
+    if (own[d] == 0 && is_nee(pr->face[2 * d])) {
+      face = 2 * d;
+      src[d] = 1;
+    } else if (own[d] == dim[d] - 1 && is_nee(pr->face[2 * d + 1])) {
+      face = 2 * d + 1;
+      src[d] = dim[d] - 2;
+    }
+    if (face < 0) continue;
+    on = 1;
+    if (pr->face[face] == 3) vface = face; /* later axes overwrite: z > y > x */
+    else pface = face;
+  }
+  if (!on) return 0;
+  {
+    const size_t m = (size_t)src[0] + (size_t)pr->nx * ((size_t)src[1] + (size_t)pr->ny * src[2]);
+    const size_t n = (size_t)x + (size_t)pr->nx * ((size_t)y + (size_t)pr->ny * z);
+    force_at(pr, t, F);
+    for (a = 0; a < L->q; ++a) fn[a] = f[(size_t)a * N + m];
+    macro_node(L, fn, F, &pf, uf);
+    feq_node(L, pf, uf, fe);
+    for (d = 0; d < 3; ++d) ub[d] = vface >= 0 ? pr->wall_u[vface][d] : uf[d];
+    pb = pface >= 0 ? face_pressure(pr, pface, t) : pf;
+    {
+      double eb[QMAX];
+      feq_node(L, pb, ub, eb);
+      for (a = 0; a < L->q; ++a) f[(size_t)a * N + n] = eb[a] + (fn[a] - fe[a]);
+    }
+  }
+  return 1;
 }
 
 /* ---- the lattice step ------------------------------------------------ */
@@ -359,7 +430,7 @@ static void step_impl(const orc_problem* pr, const lattice* L, long long t,
           int dst[3] = {x + L->c[a][0], y + L->c[a][1], z + L->c[a][2]};
           int dim[3] = {nx, ny, nz};
           int own[3] = {x, y, z};
-          int out[3] = {0, 0, 0}, outside = 0, flip[3] = {0, 0, 0}, mirrored = 0;
+          int out[3] = {0, 0, 0}, outside = 0, flip[3] = {0, 0, 0}, mirrored = 0, leaves = 0;
           for (d = 0; d < 3; ++d) {
             int face;
             if (dst[d] >= 0 && dst[d] < dim[d]) continue;
@@ -369,12 +440,19 @@ static void step_impl(const orc_problem* pr, const lattice* L, long long t,
             } else if (pr->face[face] == 2) {
               flip[d] = 1;
               mirrored = 1;
-            } else {
+            } else if (pr->face[face] == 1) {
               out[d] = (dst[d] < 0) ? -1 : 1;
               outside = 1;
+            } else {
+              leaves = 1; /* through a velocity / pressure face: lost */
             }
           }
-          if (!outside && mirrored) {
+          /* (a population leaving through an extrapolation face starts on
+             a boundary node, all of whose populations the boundary pass
+             below replaces, so it is simply dropped) */
+          if (leaves) {
+            continue;
+          } else if (!outside && mirrored) {
             int b = mirror_of(L, a, flip);
             size_t m;
             for (d = 0; d < 3; ++d)
@@ -399,6 +477,16 @@ static void step_impl(const orc_problem* pr, const lattice* L, long long t,
           }
         }
       }
+  }
+  /* boundary pass at level t+1 (reads only inward neighbours, which are
+     never boundary nodes, and writes only boundary nodes) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+  for (z = 0; z < nz; ++z) {
+    int x, y;
+    for (y = 0; y < ny; ++y)
+      for (x = 0; x < nx; ++x) nee_node(pr, L, t + 1, x, y, z, fout);
   }
 }
 

@@ -21,6 +21,7 @@ class Problem(C.Structure):
         ("wall_u", (C.c_double * 3) * 6),
         ("F0", C.c_double * 3), ("FA", C.c_double * 3),
         ("FT", C.c_double),
+        ("face_p0", C.c_double * 6), ("face_pA", C.c_double * 6),
     ]
 
 
@@ -105,15 +106,22 @@ def collide(q, s, f, F=(0.0, 0.0, 0.0)):
 
 
 def problem(q, nx, ny, nz, s, faces=("periodic",) * 6, wall_u=None,
-            F0=(0.0, 0.0, 0.0), FA=(0.0, 0.0, 0.0), FT=0.0):
-    """faces: 6 entries 'periodic'/'wall'/'symmetry' in the order -x,+x,-y,+y,-z,+z;
-    wall_u: dict face-name -> (ux,uy,uz) or a 6x3 array."""
+            F0=(0.0, 0.0, 0.0), FA=(0.0, 0.0, 0.0), FT=0.0, face_p=None, face_pA=None):
+    """faces: 6 entries 'periodic'/'wall'/'symmetry'/'velocity'/'pressure' in
+    the order -x,+x,-y,+y,-z,+z; wall_u: dict face-name -> (ux,uy,uz) or a
+    6x3 array (walls and velocity faces); face_p / face_pA: dict face-name ->
+    pressure p0 / amplitude pA of a pressure face, p(t) = p0 + pA cos(2 pi t/FT)."""
     pr = Problem()
     pr.q, pr.nx, pr.ny, pr.nz = q, nx, ny, nz
     for k in range(q):
         pr.s[k] = float(s[k])
     for i, fk in enumerate(faces):
-        pr.face[i] = {"periodic": 0, "wall": 1, "symmetry": 2, 0: 0, 1: 1, 2: 2}[fk]
+        pr.face[i] = {"periodic": 0, "wall": 1, "symmetry": 2, "velocity": 3, "pressure": 4,
+                      0: 0, 1: 1, 2: 2, 3: 3, 4: 4}[fk]
+    for name, v in (face_p or {}).items():
+        pr.face_p0[FACES.index(name)] = float(v)
+    for name, v in (face_pA or {}).items():
+        pr.face_pA[FACES.index(name)] = float(v)
     if wall_u is not None:
         if isinstance(wall_u, dict):
             for name, v in wall_u.items():
