@@ -67,14 +67,39 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2 } lbm_storage;
  * step (read and write a node's own slots) and a neighbour step. */
 typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
 
-/* Boundary kind of a lattice face.  LBM_SYMMETRY is the symmetry plane of
- * Eq. (z05symmetry) (Sec. 4.3 computes half the cavity with it): a
- * population leaving through it is reflected specularly half-way across
- * the link, f_a'(x + c_a with the crossed normal components removed, t+1) =
- * f*_a(x), where c_a' is c_a with those normal components negated.  A link
- * crossing a wall and a symmetry plane at once bounces back at the wall.
- * wall_u is ignored on periodic and symmetry faces. */
-typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_SYMMETRY = 2 } lbm_face_kind;
+/* Boundary kind of a lattice face.
+ *
+ * LBM_WALL: half-way bounce-back (above); the wall lies half a spacing
+ * beyond the last node layer.
+ *
+ * LBM_SYMMETRY is the symmetry plane of Eq. (z05symmetry) (Sec. 4.3 computes
+ * half the cavity with it): a population leaving through it is reflected
+ * specularly half-way across the link, f_a'(x + c_a with the crossed normal
+ * components removed, t+1) = f*_a(x), where c_a' is c_a with those normal
+ * components negated.  A link crossing a wall and a symmetry plane at once
+ * bounces back at the wall.
+ *
+ * LBM_VELOCITY and LBM_PRESSURE are the non-equilibrium extrapolation
+ * boundaries the paper uses throughout Sec. 4 (Guo, Zheng & Shi): the face
+ * runs through the last node layer (node-based grid: a duct of width 2a at
+ * spacing dx has 2a/dx + 1 nodes across).  After every step each node x_b on
+ * such faces is set to f(x_b) = f_eq(p_b, u_b) + [f(x_f) - f_eq(p_f, u_f)],
+ * x_f = x_b + the inward normals of its faces (p_f, u_f: the macroscopic
+ * fields there, Eq. (hgl)).  A velocity face fixes u_b = wall_u and takes
+ * p_b = p_f; a pressure face fixes p_b = face_p + face_pA cos(2 pi t / FT)
+ * (FT > 0, else face_p) at the new time level and takes u_b = u_f.  At edges
+ * and corners both kinds apply; among faces of one kind the z face wins,
+ * then y, then x.  An axis with such a face needs at least 3 nodes.  Single
+ * lattices only (batches reject them).
+ *
+ * wall_u is used on wall and velocity faces and ignored elsewhere. */
+typedef enum {
+  LBM_PERIODIC = 0,
+  LBM_WALL = 1,
+  LBM_SYMMETRY = 2,
+  LBM_VELOCITY = 3,
+  LBM_PRESSURE = 4
+} lbm_face_kind;
 
 /* Rounding of LBM_F16DEV stores made by a time step.  Stochastic (the
  * default): a value rounds up with probability equal to its distance from
@@ -107,7 +132,7 @@ typedef enum {
 /* Faces in the order -x, +x, -y, +y, -z, +z. */
 typedef struct {
   int face[6];          /* lbm_face_kind; periodic faces must come in pairs   */
-  double wall_u[6][3];  /* velocity of each wall face (0 = no-slip)          */
+  double wall_u[6][3];  /* velocity of each wall / velocity face (0: at rest) */
   double F0[3];         /* body force F(t) = F0 + FA cos(2 pi t / FT)         */
   double FA[3];
   double FT;            /* FT <= 0: constant force F0                        */
@@ -122,6 +147,8 @@ typedef struct {
   void* stream;         /* hipStream_t to queue work on (NULL: null stream)  */
   void* dev_buf;        /* optional caller-owned device buffer ...           */
   size_t dev_buf_bytes; /* ... and its size (>= lbm_footprint_bytes)         */
+  double face_p[6];     /* pressure of each LBM_PRESSURE face ...            */
+  double face_pA[6];    /* ... plus face_pA cos(2 pi t / FT) when FT > 0     */
 } lbm_spec;
 
 /* Defaults: all six faces walls at rest, no force, p0 = 0, u0 = 0, FP32,
@@ -129,8 +156,9 @@ typedef struct {
  * no monitor, null stream, own memory. */
 void lbm_spec_default(lbm_spec* spec);
 
-/* Device bytes a context of this shape needs (populations, monitor
- * snapshot and reduction scratch); 0 on invalid input.  For admission
+/* Device bytes a context of this shape needs (populations, the list of
+ * velocity/pressure-face nodes, monitor snapshot and reduction scratch); 0
+ * on invalid input.  For admission
  * control: no device call is made. */
 size_t lbm_footprint_bytes(int model, int nx, int ny, int nz, const lbm_spec* spec);
 
@@ -205,8 +233,9 @@ int lbm_destroy(lbm_ctx* ctx);
 
 /* ---- batched execution ------------------------------------------------
  * A batch advances many independent contexts (any mix of q = 14 / 18,
- * storage FP32 / FP16DEV, pattern AA, shapes, boundaries, forces and
- * rates) with one kernel launch per time step covering all of them; each
+ * storage FP32 / FP16DEV, pattern AA, MRT collision, shapes, periodic /
+ * wall / symmetry faces, forces and rates) with one kernel launch per time
+ * step and (q, storage) class covering all of them; each
  * member keeps its own time level, parity and populations, and its result
  * is bit-identical to running it alone in a batch.  Members must share the
  * batch's stream.  Members can be added and removed between calls

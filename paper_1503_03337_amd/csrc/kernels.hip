@@ -570,6 +570,137 @@ hipError_t launch_init_eq(int q, int storage, const void* args, const double* p,
   DISPATCH_QST(q, storage, return (init_impl<Q_, ST_>(args, p, u, p0, u0, s)));
 }
 
+// ---- non-equilibrium extrapolation (velocity / pressure faces) --------------
+// Eq. (edf) in the compute type: f_a = 3 w_a p + w_a (3 c.u + 9/2 (c.u)^2
+// - 3/2 |u|^2).
+template <int Q, typename C>
+__device__ __forceinline__ void feq_c(C p, C ux, C uy, C uz, C (&fe)[Q]) {
+  using L = Lattice<Q>;
+  const C usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const C w = (C)weight<Q>(a);
+    const C cu = (C)L::cx[a] * ux + (C)L::cy[a] * uy + (C)L::cz[a] * uz;
+    fe[a] = C(3) * w * p + w * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq);
+  }
+}
+
+// Store the physical populations f of node n in the layout of PHASE: the
+// exact inverse of read_node's addressing (each physical population of
+// each node has one slot, so stores for one node never touch a slot that
+// represents another node's population).
+template <int Q, int ST, int PHASE>
+__device__ __forceinline__ void store_node(const LatticeArgs<typename Codec<ST>::C>& A,
+                                           typename Codec<ST>::S* dst, unsigned n, int x, int y,
+                                           int z, const typename Codec<ST>::C (&f)[Q], unsigned h) {
+  using C = typename Codec<ST>::C;
+  using L = Lattice<Q>;
+  const long long st = A.stride;
+  if (PHASE == 0) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) pop_store(dst + a * st + n, enc_step<ST>(A, f[a], a, h, a));
+  } else {
+    const Nbr b = make_nbr<true>(A, x, y, z);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int o = L::opp[a];
+      int off, slot;
+      bool wall;
+      C term;
+      link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term, slot);
+      const long long idx = wall ? (a * st + n) : (slot * st + (long long)(n + off));
+      pop_store(dst + idx, enc_step<ST>(A, f[a], a, h, a));
+    }
+  }
+}
+
+// One thread per listed boundary node x_b: inward neighbour x_f (never on a
+// velocity / pressure face itself, as each such axis has >= 3 nodes), its
+// p_f, u_f (Eq. (hgl), u = sum c f + F/2) and f_neq = f(x_f) - f_eq(p_f, u_f);
+// then f(x_b) = f_eq(p_b, u_b) + f_neq.
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> A,
+                                             NeeArgs<typename Codec<ST>::C> E,
+                                             const int* __restrict__ nodes, int count) {
+  using CD = Codec<ST>;
+  using C = typename CD::C;
+  using L = Lattice<Q>;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const unsigned n = (unsigned)nodes[i];
+    int x, y, z;
+    node_xyz(n, A.nx, A.ny, x, y, z);
+    const int own[3] = {x, y, z}, dim[3] = {A.nx, A.ny, A.nz};
+    int src[3] = {x, y, z}, vf = -1, pf = -1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int face = -1;
+      if (own[d] == 0 && (E.kind[2 * d] == 3 || E.kind[2 * d] == 4)) {
+        face = 2 * d;
+        src[d] = 1;
+      } else if (own[d] == dim[d] - 1 && (E.kind[2 * d + 1] == 3 || E.kind[2 * d + 1] == 4)) {
+        face = 2 * d + 1;
+        src[d] = dim[d] - 2;
+      }
+      if (face < 0) continue;
+      if (E.kind[face] == 3)
+        vf = face;  // later axes win: z over y over x
+      else
+        pf = face;
+    }
+    const unsigned m = (unsigned)src[0] + (unsigned)A.nx * ((unsigned)src[1] + (unsigned)A.ny * (unsigned)src[2]);
+    C ff[Q];
+    read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), m, src[0], src[1],
+                                  src[2], ff);
+    C P = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      P += ff[a];
+      if (L::cx[a]) jx += L::cx[a] > 0 ? ff[a] : -ff[a];
+      if (L::cy[a]) jy += L::cy[a] > 0 ? ff[a] : -ff[a];
+      if (L::cz[a]) jz += L::cz[a] > 0 ? ff[a] : -ff[a];
+    }
+    const C ux = jx + C(0.5) * A.F[0], uy = jy + C(0.5) * A.F[1], uz = jz + C(0.5) * A.F[2];
+    const C w0 = (C)L::w0;
+    const C pf_ = (P - C(1.5) * w0 * (ux * ux + uy * uy + uz * uz)) / (C(3) * (C(1) - w0));
+    C fe[Q], fb[Q];
+    feq_c<Q, C>(pf_, ux, uy, uz, fe);
+    C bx = ux, by = uy, bz = uz, pb = pf_;
+    if (vf >= 0) {
+      bx = E.u[vf][0];
+      by = E.u[vf][1];
+      bz = E.u[vf][2];
+    }
+    if (pf >= 0) pb = E.p[pf];
+    feq_c<Q, C>(pb, bx, by, bz, fb);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) fb[a] += ff[a] - fe[a];
+    store_node<Q, ST, PHASE>(A, static_cast<typename CD::S*>(A.f), n, x, y, z, fb,
+                             node_hash(n, A.tstep) ^ 0x68E31DA4u);
+  }
+}
+
+template <int Q, int ST>
+static hipError_t nee_impl(int phase, const void* args, const void* nee, const int* nodes,
+                           int count, hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const NeeArgs<C>& E = *static_cast<const NeeArgs<C>*>(nee);
+  if (count <= 0) return hipSuccess;
+  const int nb = aux_blocks(count);
+  if (phase == 0)
+    hipLaunchKernelGGL((k_nee<Q, ST, 0>), dim3(nb), dim3(256), 0, s, A, E, nodes, count);
+  else
+    hipLaunchKernelGGL((k_nee<Q, ST, 1>), dim3(nb), dim3(256), 0, s, A, E, nodes, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_nee(int q, int storage, int phase, const void* args, const void* nee,
+                      const int* nodes, int count, hipStream_t s) {
+  clear_stale_error();
+  DISPATCH_QST(q, storage, return (nee_impl<Q_, ST_>(phase, args, nee, nodes, count, s)));
+}
+
 // ---- macroscopic fields and monitors ----------------------------------------
 // P = sum f, j = sum c f (FP64 sums of the decoded values), u = j + F/2,
 // p by Eq. (hgl).

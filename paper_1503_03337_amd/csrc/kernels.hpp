@@ -53,6 +53,14 @@ template <typename C> struct LatticeArgs {
   C omega, hom;            // LBGK collision: 1/tau, 1 - 1/(2 tau)
 };
 
+// Boundary values of the velocity / pressure faces (non-equilibrium
+// extrapolation) at the time level being completed.
+template <typename C> struct NeeArgs {
+  int kind[6];   // 3 velocity face, 4 pressure face, anything else: neither
+  C u[6][3];     // velocity of a velocity face
+  C p[6];        // pressure of a pressure face at this level
+};
+
 // Launches (all asynchronous on `stream`; return a hipError_t).
 hipError_t launch_step(int q, int storage, int mode, bool forced, const void* args,
                        size_t args_bytes, hipStream_t stream);
@@ -63,6 +71,12 @@ hipError_t launch_step_bgk(int q, int storage, int mode, bool forced, const void
 // swapped) into FP64 out[N].
 hipError_t launch_get_pop(int q, int storage, int phase, int a, const void* args, double* out,
                           hipStream_t stream);
+// Non-equilibrium extrapolation on the `count` nodes listed in `nodes`
+// (linear indices of the nodes on velocity / pressure faces), in the layout
+// of `phase` (0 natural, 1 AA swapped), with args.F = F and args.tstep = t
+// of the level just reached; nee points to NeeArgs of the compute type.
+hipError_t launch_nee(int q, int storage, int phase, const void* args, const void* nee,
+                      const int* nodes, int count, hipStream_t stream);
 // Encode FP64 in[N] into population a (natural layout).
 hipError_t launch_set_pop(int q, int storage, int a, const void* args, const double* in,
                           hipStream_t stream);

@@ -50,6 +50,22 @@ size_t population_bytes(int q, size_t N, int storage) {
   return (size_t)q * pop_stride(N) * (size_t)bytes_of(storage);
 }
 
+bool is_nee_face(int kind) { return kind == LBM_VELOCITY || kind == LBM_PRESSURE; }
+
+// Number of nodes on velocity / pressure faces: all nodes minus the box of
+// nodes on none of them.
+long long nee_node_count(int nx, int ny, int nz, const lbm_spec* sp) {
+  const int dim[3] = {nx, ny, nz};
+  long long inner = 1;
+  bool any = false;
+  for (int d = 0; d < 3; ++d) {
+    const int lo = is_nee_face(sp->face[2 * d]), hi = is_nee_face(sp->face[2 * d + 1]);
+    any = any || lo || hi;
+    inner *= std::max(0, dim[d] - lo - hi);
+  }
+  return any ? (long long)nx * ny * nz - inner : 0;
+}
+
 std::string validate(int model, int nx, int ny, int nz, const double* s, const lbm_spec* sp) {
   if (model != 14 && model != 18) return "model must be 14 or 18";
   if (nx < 1 || ny < 1 || nz < 1) return "lattice dimensions must be >= 1";
@@ -70,10 +86,17 @@ std::string validate(int model, int nx, int ny, int nz, const double* s, const l
   }
   for (int d = 0; d < 3; ++d) {
     const int a = sp->face[2 * d], b = sp->face[2 * d + 1];
-    if (a < LBM_PERIODIC || a > LBM_SYMMETRY || b < LBM_PERIODIC || b > LBM_SYMMETRY)
-      return "face kind must be LBM_PERIODIC, LBM_WALL or LBM_SYMMETRY";
+    if (a < LBM_PERIODIC || a > LBM_PRESSURE || b < LBM_PERIODIC || b > LBM_PRESSURE)
+      return "face kind must be LBM_PERIODIC, LBM_WALL, LBM_SYMMETRY, LBM_VELOCITY or "
+             "LBM_PRESSURE";
     if ((a == LBM_PERIODIC) != (b == LBM_PERIODIC)) return "periodic faces must come in pairs";
+    const int dim[3] = {nx, ny, nz};
+    if ((is_nee_face(a) || is_nee_face(b)) && dim[d] < 3)
+      return "an axis with a velocity or pressure face needs at least 3 nodes";
   }
+  for (int f = 0; f < 6; ++f)
+    if (!std::isfinite(sp->face_p[f]) || !std::isfinite(sp->face_pA[f]))
+      return "face pressures must be finite";
   for (int f = 0; f < 6; ++f) {
     const double* u = sp->wall_u[f];
     const double m = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -146,6 +169,11 @@ struct lbm_ctx {
   int tx = 1, ty = 1;
   LatticeArgs<double> a64{};
   LatticeArgs<float> a32{};
+  // velocity / pressure faces: the nodes on them (in buf) and their values
+  int* nee_nodes = nullptr;
+  int nee_count = 0;
+  NeeArgs<double> e64{};
+  NeeArgs<float> e32{};
   std::string err;
   void* batch = nullptr;  // batch this context belongs to (or NULL)
 };
@@ -324,6 +352,7 @@ size_t lbm_footprint_bytes(int model, int nx, int ny, int nz, const lbm_spec* sp
   const size_t N = (size_t)nx * ny * nz;
   size_t b = align_up(population_bytes(model, N, sp->storage));
   if (sp->pattern == LBM_AB) b *= 2;
+  b += align_up(sizeof(int) * (size_t)nee_node_count(nx, ny, nz, sp));
   if (sp->monitor_every > 0) b += monitor_bytes(N, sp->storage);
   return b;
 }
@@ -390,6 +419,45 @@ int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz, const double* s
   c->popA = base;
   c->popB = sp->pattern == LBM_AB ? base + pop : nullptr;
   size_t off = pop * (sp->pattern == LBM_AB ? 2 : 1);
+  c->nee_count = (int)nee_node_count(nx, ny, nz, sp);
+  if (c->nee_count > 0) {
+    // nodes on velocity / pressure faces, in increasing linear index
+    std::vector<int> list;
+    list.reserve((size_t)c->nee_count);
+    auto on = [&](int v, int n, int d) {
+      return (v == 0 && is_nee_face(sp->face[2 * d])) ||
+             (v == n - 1 && is_nee_face(sp->face[2 * d + 1]));
+    };
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y) {
+        const bool row = on(z, nz, 2) || on(y, ny, 1);
+        const int base_n = nx * (y + ny * z);
+        if (row) {
+          for (int x = 0; x < nx; ++x) list.push_back(base_n + x);
+        } else {
+          if (on(0, nx, 0)) list.push_back(base_n);
+          if (nx > 1 && on(nx - 1, nx, 0)) list.push_back(base_n + nx - 1);
+        }
+      }
+    c->nee_nodes = (int*)(base + off);
+    off += align_up(sizeof(int) * list.size());
+    hipError_t e = list.size() == (size_t)c->nee_count
+                       ? hipMemcpy(c->nee_nodes, list.data(), sizeof(int) * list.size(),
+                                   hipMemcpyHostToDevice)
+                       : hipErrorInvalidValue;
+    if (e != hipSuccess) {
+      g_create_err = std::string("boundary node list: ") + hipGetErrorString(e);
+      lbm_destroy(c);
+      return LBM_EDEVICE;
+    }
+    for (int f = 0; f < 6; ++f) {
+      c->e64.kind[f] = c->e32.kind[f] = sp->face[f];
+      for (int d = 0; d < 3; ++d) {
+        c->e64.u[f][d] = sp->wall_u[f][d];
+        c->e32.u[f][d] = (float)sp->wall_u[f][d];
+      }
+    }
+  }
   if (sp->monitor_every > 0) {
     const size_t snap_b = align_up(3 * c->N * (sp->storage == LBM_F64 ? 8 : 4));
     const size_t part_b = align_up(3 * sizeof(double) * 2048);
@@ -435,6 +503,21 @@ int lbm_step(lbm_ctx* c, long long n) {
       c->phase ^= 1;
     }
     c->t += 1;
+    if (c->nee_count > 0) {
+      // velocity / pressure faces at the level just reached
+      set_force(*c, c->t);
+      for (int f = 0; f < 6; ++f) {
+        double pf = c->spec.face_p[f];
+        if (c->spec.FT > 0.0)
+          pf += c->spec.face_pA[f] * std::cos(2.0 * M_PI * (double)c->t / c->spec.FT);
+        c->e64.p[f] = pf;
+        c->e32.p[f] = (float)pf;
+      }
+      const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
+      const void* e = c->spec.storage == LBM_F64 ? (const void*)&c->e64 : (const void*)&c->e32;
+      HIPCHK(c, launch_nee(c->q, c->spec.storage, phase, args_ptr(*c), e, c->nee_nodes,
+                           c->nee_count, c->stream));
+    }
     if (K > 0 && c->t % K == 0) {
       const int rc = run_monitor(c);
       if (rc) return rc;
@@ -716,6 +799,8 @@ int lbm_batch_add(lbm_batch* b, lbm_ctx* c, long long budget) {
     return bfail(b, LBM_EINVAL, "batched members must store LBM_F32 or LBM_F16DEV");
   if (c->stream != b->stream) return bfail(b, LBM_EINVAL, "member stream differs from batch stream");
   if (c->spec.collision != LBM_MRT) return bfail(b, LBM_EINVAL, "batched members use LBM_MRT");
+  if (c->nee_count > 0)
+    return bfail(b, LBM_EINVAL, "velocity / pressure faces are not batched (single lattices only)");
   b->members.push_back(Member{c, budget, 0, 0});
   c->batch = b;
   return LBM_OK;

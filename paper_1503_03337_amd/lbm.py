@@ -24,7 +24,7 @@ STORAGE = {"f64": 0, "f32": 1, "f16dev": 2}
 ROUNDING = {"stochastic": 0, "nearest": 1}
 COLLISION = {"mrt": 0, "bgk": 1}
 PATTERN = {"ab": 0, "aa": 1}
-FACE_KIND = {"periodic": 0, "wall": 1, "symmetry": 2}
+FACE_KIND = {"periodic": 0, "wall": 1, "symmetry": 2, "velocity": 3, "pressure": 4}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
 
@@ -53,6 +53,8 @@ class Spec(C.Structure):
         ("stream", C.c_void_p),
         ("dev_buf", C.c_void_p),
         ("dev_buf_bytes", C.c_size_t),
+        ("face_p", C.c_double * 6),
+        ("face_pA", C.c_double * 6),
     ]
 
 
@@ -134,7 +136,10 @@ def _dptr(a):
 
 def make_spec(faces=("wall",) * 6, wall_u=None, F0=(0, 0, 0), FA=(0, 0, 0), FT=0.0, p0=0.0,
               u0=(0, 0, 0), storage="f32", pattern="aa", f16_scale_log2=12,
-              f16_rounding="stochastic", collision="mrt", monitor_every=0, stream=None):
+              f16_rounding="stochastic", collision="mrt", monitor_every=0, stream=None,
+              face_p=None, face_pA=None):
+    """face_p / face_pA: {face name: value} pressures of pressure faces,
+    p(t) = face_p + face_pA cos(2 pi t / FT)."""
     sp = Spec()
     lib().lbm_spec_default(C.byref(sp))
     for k, fk in enumerate(faces):
@@ -162,6 +167,10 @@ def make_spec(faces=("wall",) * 6, wall_u=None, F0=(0, 0, 0), FA=(0, 0, 0), FT=0
     sp.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     sp.monitor_every = int(monitor_every)
     sp.stream = stream
+    for name, v in (face_p or {}).items():
+        sp.face_p[FACES.index(name)] = float(v)
+    for name, v in (face_pA or {}).items():
+        sp.face_pA[FACES.index(name)] = float(v)
     return sp
 
 

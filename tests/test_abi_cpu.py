@@ -59,8 +59,10 @@ def test_footprint_without_device():
     dict(model=15), dict(nx=0), dict(faces=("periodic", "wall") + ("wall",) * 4),
     dict(wall_u={"+z": (0.3, 0, 0)}), dict(storage=7), dict(pattern=5),
     dict(storage="f16dev", f16_scale_log2=30), dict(monitor_every=-1),
-    dict(faces=("periodic", "symmetry") + ("wall",) * 4), dict(faces=(3,) + ("wall",) * 5),
+    dict(faces=("periodic", "symmetry") + ("wall",) * 4), dict(faces=(5,) + ("wall",) * 5),
     dict(faces=("wall",) * 5 + (-1,)),
+    dict(nx=2, faces=("pressure", "pressure") + ("velocity",) * 4),
+    dict(faces=("pressure", "wall") + ("wall",) * 4, face_p={"-x": float("nan")}),
 ])
 def test_footprint_rejects_invalid(bad):
     from paper_1503_03337_amd import lbm
@@ -119,3 +121,15 @@ def test_footprint_accepts_symmetry_faces():
     for faces in (("wall",) * 5 + ("symmetry",),
                   ("symmetry", "symmetry", "periodic", "periodic", "wall", "symmetry")):
         assert lbm.footprint_bytes(18, 8, 8, 8, faces=faces) > 0
+
+
+def test_footprint_holds_the_boundary_node_list():
+    """Velocity / pressure faces add the list of their nodes (int32) to the
+    footprint: 17 x 9 x 9 duct, every face of that kind -> all nodes but the
+    15 x 7 x 7 inner box."""
+    from paper_1503_03337_amd import lbm
+    faces = ("pressure", "pressure") + ("velocity",) * 4
+    walls = lbm.footprint_bytes(14, 17, 9, 9, faces=("wall",) * 6, storage="f64")
+    nee = lbm.footprint_bytes(14, 17, 9, 9, faces=faces, storage="f64")
+    count = 17 * 9 * 9 - 15 * 7 * 7
+    assert nee - walls == (4 * count + 255) // 256 * 256

@@ -1,0 +1,174 @@
+"""Velocity / pressure faces (non-equilibrium extrapolation, the boundary
+scheme of the paper's Sec. 4) on the GPU, through the C ABI:
+
+* element-wise against the FP64 oracle on random states, every step of
+  both AA parities and AB, with time-dependent face pressure, a moving
+  velocity face, body force, and mixed with walls, symmetry planes and
+  periodic axes (FP64 1e-13 of max|f|; FP32 / FP16 at their storage
+  tolerances);
+* AA == AB bit for bit;
+* the paper's own numbers: every entry of Table 1 (steady Poiseuille,
+  Sec. 4.1, dx = 1/8 .. 1/64, 1/tau = 0.8, 1.0, 1.3) and Table 2
+  (pulsatile, Sec. 4.2, dx = 1/20 .. 1/80, four phases) to the last
+  printed digit, against the analytic series.
+"""
+import numpy as np
+import pytest
+
+from helpers import (NEE_FACES, node_positions, paper_gre, paper_poiseuille, paper_pulsatile,
+                     printed_table, svec, within_last_digit)
+from oracle import analytic as A
+from oracle import runner as R
+from paper_1503_03337_amd import inputs
+from paper_1503_03337_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+SETUPS = {
+    # name: (dims, faces, wall_u, face_p, face_pA, F0, FT)
+    "duct": ((13, 9, 7), NEE_FACES, {"+z": (0.03, 0.0, 0.01)}, {"-x": 0.004, "+x": -0.003},
+             {"-x": 0.002}, (0, 0, 0), 9.0),
+    "mixed": ((11, 7, 6), ("pressure", "velocity", "wall", "symmetry", "periodic", "periodic"),
+              {"+x": (0.02, 0.01, 0.0), "-y": (0.05, 0.0, 0.0)}, {"-x": 0.002}, None,
+              (1e-5, 0.0, 2e-5), 0.0),
+    "corners": ((9, 8, 7), ("velocity", "pressure", "pressure", "velocity", "velocity", "pressure"),
+                {"-x": (0.01, 0.0, 0.0), "+y": (0.0, 0.0, 0.02), "-z": (0.02, 0.01, 0.0)},
+                {"+x": 0.001, "-y": -0.002, "+z": 0.003}, None, (0, 0, 0), 0.0),
+    "long": ((300, 3, 4), ("pressure", "pressure", "periodic", "periodic", "velocity", "velocity"),
+             None, {"-x": 0.003, "+x": 0.0}, None, (0, 0, 0), 0.0),
+}
+
+
+def rates(q):
+    return svec(q, 1.35) + np.linspace(-0.03, 0.03, q)
+
+
+def make(q, setup, storage, pattern, seed=0):
+    dims, faces, wall_u, fp, fpa, F0, FT = SETUPS[setup]
+    kw = dict(faces=faces, wall_u=wall_u, face_p=fp, face_pA=fpa, F0=F0, FT=FT)
+    lat = lbm.Lattice(q, *dims, rates(q), storage=storage, pattern=pattern, **kw)
+    pr = R.problem(q, *dims, rates(q), **kw)
+    lat.set_f(inputs.random_populations(q, *dims, seed=seed))
+    return lat, pr
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("setup", sorted(SETUPS))
+def test_fp64_matches_oracle(q, pattern, setup):
+    lat, pr = make(q, setup, "f64", pattern)
+    f = lat.get_f()
+    scale = np.max(np.abs(f))
+    for t in range(1, 6):
+        lat.step(1)
+        f = R.run(pr, f, t - 1, 1)
+        g = lat.get_f()
+        assert np.max(np.abs(g - f)) <= 1e-13 * scale, (setup, pattern, t)
+    p, u = lat.macros()
+    pr_, ur = R.macros(pr, f, 5)
+    assert np.max(np.abs(u - ur)) <= 1e-13 and np.max(np.abs(p - pr_)) <= 1e-13
+    lat.close()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("storage", ("f32", "f16dev"))
+@pytest.mark.parametrize("setup", ("duct", "corners"))
+def test_reduced_storage_matches_oracle(q, storage, setup):
+    lat, pr = make(q, setup, storage, "aa")
+    f = lat.get_f()
+    lat.step(6)
+    f = R.run(pr, f, 0, 6)
+    g = lat.get_f()
+    err = np.linalg.norm(g - f) / np.linalg.norm(f)
+    # FP32: unit roundoff 6e-8 over a few hundred operations; FP16 deviations:
+    # one rounding (2^-10 relative, stochastic) per value and step
+    assert err <= (1e-6 if storage == "f32" else 2 * np.sqrt(6) * 2.0 ** -10), err
+    lat.close()
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("storage", ("f64", "f32"))
+@pytest.mark.parametrize("setup", sorted(SETUPS))
+def test_aa_equals_ab_bit_exact(q, storage, setup):
+    out = {}
+    for pattern in ("aa", "ab"):
+        lat, _ = make(q, setup, storage, pattern, seed=3)
+        lat.step(7)
+        out[pattern] = lat.get_f()
+        lat.close()
+    assert np.array_equal(out["aa"], out["ab"])
+
+
+def test_batches_reject_velocity_and_pressure_faces():
+    q = 14
+    lat = lbm.Lattice(q, 9, 7, 7, svec(q, 1.2), faces=NEE_FACES, face_p={"-x": 0.001},
+                      storage="f32")
+    b = lbm.Batch(lat.stream)
+    with pytest.raises(lbm.LbmError):
+        b.add(lat, 10)
+    b.close()
+    lat.close()
+
+
+def run_poiseuille(dx, inv_tau, storage="f64"):
+    q = 14
+    S = paper_poiseuille(dx, inv_tau)
+    nx, ny, nz, c = S["nx"], S["ny"], S["nz"], S["c"]
+    lat = lbm.Lattice(q, nx, ny, nz, svec(q, S["s_nu"]), faces=NEE_FACES, face_p=S["face_p"],
+                      storage=storage, pattern="aa")
+    lat.init_fields(np.full((nz, ny, nx), S["p_init"]), np.zeros((3, nz, ny, nx)))
+    res, every = 1.0, 200
+    while res > 1e-10:
+        lat.step(every - 1)
+        u1 = lat.macros()[1][0]
+        lat.step(1)
+        u = lat.macros()[1]
+        res = np.sum(np.abs(u[0] - u1)) / np.sum(np.abs(u1))
+        assert lat.time < 200000
+    steps = lat.time
+    lat.close()
+    y = node_positions(ny)
+    Y, Z = np.meshgrid(y, y, indexing="xy")
+    ua = A.duct_steady(Y, Z, 0.5, 0.5, S["g_phys"], S["nu_phys"])
+    ua[0, :] = ua[-1, :] = ua[:, 0] = ua[:, -1] = 0.0
+    return paper_gre(u, c, ua), steps
+
+
+@pytest.mark.parametrize("inv_tau", ("0.8", "1.0", "1.3"))
+@pytest.mark.parametrize("k,dx", [(0, 1 / 8), (1, 1 / 16), (2, 1 / 32), (3, 1 / 64)])
+def test_table1_poiseuille_reproduced(inv_tau, k, dx):
+    """Sec. 4.1 / Table 1 (iD3Q14, FP64, steady state by Eq. (sc) at 1e-10)."""
+    gre, steps = run_poiseuille(dx, float(inv_tau))
+    printed = printed_table("table1")[inv_tau][k]
+    print("GPU Table 1, 1/tau=%s dx=1/%d: GRE %.5e printed %.3e (%d steps)" % (
+        inv_tau, round(1 / dx), gre, printed, steps))
+    assert within_last_digit(gre, printed)
+
+
+@pytest.mark.parametrize("k,inv", [(0, 20), (1, 40), (2, 60), (3, 80)])
+def test_table2_pulsatile_reproduced(k, inv):
+    """Sec. 4.2 / Table 2 (iD3Q14, FP64): four periods from rest, then GRE_u
+    at T/4, T/2, 3T/4, T (analytic Eq. (wa), 0 on the wall nodes)."""
+    q = 14
+    S = paper_pulsatile(1.0 / inv)
+    nx, ny, nz, c, per = S["nx"], S["ny"], S["nz"], S["c"], S["steps_per_period"]
+    lat = lbm.Lattice(q, nx, ny, nz, svec(q, S["s_nu"]), faces=NEE_FACES, face_p=S["face_p"],
+                      face_pA=S["face_pA"], FT=float(per), storage="f64", pattern="aa")
+    lat.init_fields(np.full((nz, ny, nx), S["p_init"]), np.zeros((3, nz, ny, nx)))
+    lat.step(4 * per)
+    y = node_positions(ny)
+    Y, Z = np.meshgrid(y, y, indexing="xy")
+    printed = printed_table("table2")
+    out = []
+    for name, ph in (("T/4", per // 4), ("T/2", per // 2), ("3T/4", 3 * per // 4), ("T", per)):
+        lat.step(4 * per + ph - lat.time)
+        u = lat.macros()[1]
+        ua = A.duct_pulsatile(Y, Z, lat.time * S["dt"], 0.5, 0.5, -S["G"], S["nu_phys"],
+                              S["omega"], 2000)
+        ua[0, :] = ua[-1, :] = ua[:, 0] = ua[:, -1] = 0.0
+        out.append((name, paper_gre(u, c, ua), printed[name][k]))
+    lat.close()
+    for name, gre, p in out:
+        print("GPU Table 2, dx=1/%d %s: GRE %.5e printed %.3e" % (inv, name, gre, p))
+    for name, gre, p in out:
+        assert within_last_digit(gre, p), (name, gre, p)
