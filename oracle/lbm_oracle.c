@@ -45,7 +45,11 @@
  *                          equilibrium of its boundary values plus the
  *                          non-equilibrium part of its inward neighbour;
  *                          a velocity face fixes u and takes p from the
- *                          neighbour, a pressure face (Eq. (bc)) the reverse
+ *                          neighbour, a pressure face (Eq. (bc)) the reverse;
+ *   node-layer symmetry .. Eq. (z05symmetry) on a plane through the last
+ *                          node layer (the paper's 97x97x49 half cavity):
+ *                          the populations arriving from beyond the plane
+ *                          are the mirror images of those leaving towards it
  *
  * Layout: f[a*N + n], n = x + nx*(y + ny*z), a = 0..q-1 in the paper's
  * order 1..q.  Everything is FP64.  Build: -O2 -ffp-contract=off.
@@ -160,7 +164,8 @@ typedef struct {
   double s[QMAX];        /* relaxation rates in the order of Eq. (moment) */
   int face[6];           /* -x,+x,-y,+y,-z,+z: 0 periodic, 1 wall,
                             2 symmetry plane, 3 velocity face and 4
-                            pressure face (non-equilibrium extrapolation) */
+                            pressure face (non-equilibrium extrapolation),
+                            5 symmetry plane through the last node layer */
   double wall_u[6][3];   /* velocity of each wall or velocity face        */
   double F0[3], FA[3];   /* body force F(t) = F0 + FA cos(2 pi t / FT)    */
   double FT;             /* FT <= 0: constant force F0 and face pressure  */
@@ -325,11 +330,11 @@ static int check_problem(const orc_problem* pr, lattice* L) {
   if (make_lattice(pr->q, L)) return -1;
   if (pr->nx < 1 || pr->ny < 1 || pr->nz < 1) return -1;
   for (d = 0; d < 6; ++d)
-    if (pr->face[d] < 0 || pr->face[d] > 4) return -1;
+    if (pr->face[d] < 0 || pr->face[d] > 5) return -1;
   for (d = 0; d < 3; ++d) {
     if ((pr->face[2 * d] == 0) != (pr->face[2 * d + 1] == 0)) return -1;
     /* a boundary node's inward neighbour must not lie on the opposite face */
-    if ((is_nee(pr->face[2 * d]) || is_nee(pr->face[2 * d + 1])) && dim[d] < 3) return -1;
+    if ((pr->face[2 * d] >= 3 || pr->face[2 * d + 1] >= 3) && dim[d] < 3) return -1;
   }
   return 0;
 }
@@ -347,23 +352,57 @@ static int mirror_of(const lattice* L, int a, const int flip[3]) {
   return -1;
 }
 
-/* ---- non-equilibrium extrapolation ------------------------------------ */
+/* ---- node-based faces ------------------------------------------------- */
 
-/* Boundary node x_b (on one to three velocity / pressure faces) after
- * streaming to level t: its inward neighbour x_f = x_b + sum of the inward
- * normals of those faces gives p_f, u_f and f_neq = f(x_f) - f_eq(p_f, u_f);
- * then f(x_b) = f_eq(p_b, u_b) + f_neq, with u_b the velocity of a velocity
- * face (else u_f) and p_b the pressure of a pressure face (else p_f).  When
- * several faces of one kind meet at an edge or corner, the z face wins, then
- * the y face, then the x face (as for wall velocities).  Returns 0 if x_b is
- * on no such face. */
+/* Node-layer symmetry faces (pass 1 after streaming to level t): at a node
+ * x_b on such planes and on no velocity / pressure face, the populations
+ * that arrive from beyond a plane are the mirror images of those the layer
+ * below sent towards it, which streaming has just delivered to x_b as the
+ * mirrored populations: f_a(x_b) = f_m(x_b), m = a with the components
+ * normal to the crossed planes reversed.  The plane thus acts as a mirror
+ * through the node layer, and a half domain evolves exactly as the full
+ * one.  Returns 0 if x_b is not such a node. */
+static int mirror_node(const orc_problem* pr, const lattice* L, int x, int y, int z, double* f) {
+  const int dim[3] = {pr->nx, pr->ny, pr->nz};
+  const int own[3] = {x, y, z};
+  const size_t N = (size_t)pr->nx * pr->ny * pr->nz;
+  const size_t n = (size_t)x + (size_t)pr->nx * ((size_t)y + (size_t)pr->ny * z);
+  int d, a, side[3] = {0, 0, 0}, mir = 0;
+  double fn[QMAX];
+  for (d = 0; d < 3; ++d) {
+    const int lo = pr->face[2 * d], hi = pr->face[2 * d + 1];
+    if ((own[d] == 0 && is_nee(lo)) || (own[d] == dim[d] - 1 && is_nee(hi))) return 0;
+    if (own[d] == 0 && lo == 5) side[d] = -1, mir = 1;
+    if (own[d] == dim[d] - 1 && hi == 5) side[d] = 1, mir = 1;
+  }
+  if (!mir) return 0;
+  for (a = 0; a < L->q; ++a) fn[a] = f[(size_t)a * N + n];
+  for (a = 0; a < L->q; ++a) {
+    int flip[3] = {0, 0, 0}, any = 0;
+    for (d = 0; d < 3; ++d)
+      if (side[d] != 0 && L->c[a][d] * side[d] < 0) flip[d] = any = 1; /* arrives from beyond */
+    if (any) f[(size_t)a * N + n] = fn[mirror_of(L, a, flip)];
+  }
+  return 1;
+}
+
+/* Velocity / pressure faces (pass 2, non-equilibrium extrapolation): a
+ * node x_b on one or more of them takes its inward neighbour x_f = x_b + sum
+ * of the inward normals of those faces (x_f lies on no such face, but may
+ * lie on a node-layer symmetry plane, already completed by pass 1), p_f,
+ * u_f and f_neq = f(x_f) - f_eq(p_f, u_f); then f(x_b) = f_eq(p_b, u_b) +
+ * f_neq, with u_b the velocity of a velocity face (else u_f) and p_b the
+ * pressure of a pressure face (else p_f).  When several faces of one kind
+ * meet at an edge or corner, the z face wins, then the y face, then the x
+ * face (as for wall velocities).  Returns 0 if x_b is on no such face. */
 static int nee_node(const orc_problem* pr, const lattice* L, long long t, int x, int y, int z,
                     double* f) {
   const int dim[3] = {pr->nx, pr->ny, pr->nz};
   const int own[3] = {x, y, z};
   const size_t N = (size_t)pr->nx * pr->ny * pr->nz;
+  const size_t n = (size_t)x + (size_t)pr->nx * ((size_t)y + (size_t)pr->ny * z);
   int src[3] = {x, y, z}, d, a, on = 0, vface = -1, pface = -1;
-  double F[3], fn[QMAX], pf, uf[3], fe[QMAX], ub[3], pb;
+  double F[3], fn[QMAX], pf, uf[3], fe[QMAX], ub[3], pb, eb[QMAX];
   for (d = 0; d < 3; ++d) {
     int face = -1;
     if (own[d] == 0 && is_nee(pr->face[2 * d])) {
@@ -381,19 +420,15 @@ static int nee_node(const orc_problem* pr, const lattice* L, long long t, int x,
   if (!on) return 0;
   {
     const size_t m = (size_t)src[0] + (size_t)pr->nx * ((size_t)src[1] + (size_t)pr->ny * src[2]);
-    const size_t n = (size_t)x + (size_t)pr->nx * ((size_t)y + (size_t)pr->ny * z);
     force_at(pr, t, F);
     for (a = 0; a < L->q; ++a) fn[a] = f[(size_t)a * N + m];
-    macro_node(L, fn, F, &pf, uf);
-    feq_node(L, pf, uf, fe);
-    for (d = 0; d < 3; ++d) ub[d] = vface >= 0 ? pr->wall_u[vface][d] : uf[d];
-    pb = pface >= 0 ? face_pressure(pr, pface, t) : pf;
-    {
-      double eb[QMAX];
-      feq_node(L, pb, ub, eb);
-      for (a = 0; a < L->q; ++a) f[(size_t)a * N + n] = eb[a] + (fn[a] - fe[a]);
-    }
   }
+  macro_node(L, fn, F, &pf, uf);
+  feq_node(L, pf, uf, fe);
+  for (d = 0; d < 3; ++d) ub[d] = vface >= 0 ? pr->wall_u[vface][d] : uf[d];
+  pb = pface >= 0 ? face_pressure(pr, pface, t) : pf;
+  feq_node(L, pb, ub, eb);
+  for (a = 0; a < L->q; ++a) f[(size_t)a * N + n] = eb[a] + (fn[a] - fe[a]);
   return 1;
 }
 
@@ -444,12 +479,12 @@ static void step_impl(const orc_problem* pr, const lattice* L, long long t,
               out[d] = (dst[d] < 0) ? -1 : 1;
               outside = 1;
             } else {
-              leaves = 1; /* through a velocity / pressure face: lost */
+              leaves = 1; /* through a node-based face: lost */
             }
           }
-          /* (a population leaving through an extrapolation face starts on
-             a boundary node, all of whose populations the boundary pass
-             below replaces, so it is simply dropped) */
+          /* (a population leaving through a node-based face starts on a
+             boundary node; the boundary pass below replaces what would
+             arrive in its place, so it is simply dropped) */
           if (leaves) {
             continue;
           } else if (!outside && mirrored) {
@@ -478,8 +513,17 @@ static void step_impl(const orc_problem* pr, const lattice* L, long long t,
         }
       }
   }
-  /* boundary pass at level t+1 (reads only inward neighbours, which are
-     never boundary nodes, and writes only boundary nodes) */
+  /* boundary passes at level t+1: node-layer symmetry planes (each node
+     reads and writes only itself), then velocity / pressure faces (each
+     reads an inward neighbour, never on such a face, writes itself) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+  for (z = 0; z < nz; ++z) {
+    int x, y;
+    for (y = 0; y < ny; ++y)
+      for (x = 0; x < nx; ++x) mirror_node(pr, L, x, y, z, fout);
+  }
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static)
 #endif

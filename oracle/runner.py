@@ -117,7 +117,7 @@ def problem(q, nx, ny, nz, s, faces=("periodic",) * 6, wall_u=None,
         pr.s[k] = float(s[k])
     for i, fk in enumerate(faces):
         pr.face[i] = {"periodic": 0, "wall": 1, "symmetry": 2, "velocity": 3, "pressure": 4,
-                      0: 0, 1: 1, 2: 2, 3: 3, 4: 4}[fk]
+                      "symmetry_node": 5, 0: 0, 1: 1, 2: 2, 3: 3, 4: 4, 5: 5}[fk]
     for name, v in (face_p or {}).items():
         pr.face_p0[FACES.index(name)] = float(v)
     for name, v in (face_pA or {}).items():

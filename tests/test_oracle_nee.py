@@ -122,3 +122,65 @@ def test_table2_pulsatile_reproduced():
         gre = paper_gre(u, c, ua)
         print("Table 2, dx=1/20, %s: GRE %.5e printed %.3e" % (name, gre, printed[name][0]))
         assert within_last_digit(gre, printed[name][0])
+
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_node_symmetry_zero_normal_velocity(q):
+    """Node-layer symmetry face: a uniform flow along the plane is a fixed
+    point, and after a step from a random state every node of the plane
+    carries zero normal velocity (its arriving populations mirror the
+    leaving ones)."""
+    faces = ("periodic", "periodic", "velocity", "velocity", "velocity", "symmetry_node")
+    u0 = (0.02, -0.01, 0.0)
+    wall = {"-y": u0, "+y": u0, "-z": u0}
+    pr = R.problem(q, 5, 6, 7, svec(q, 1.3), faces=faces, wall_u=wall)
+    f0 = R.init_eq(pr, 0, p0=0.003, u0=u0)
+    assert np.max(np.abs(R.run(pr, f0, 0, 4) - f0)) <= 1e-15
+    rng = np.random.default_rng(8)
+    pr = R.problem(q, 5, 6, 7, svec(q, 1.3) + np.linspace(-0.02, 0.02, q), faces=faces)
+    f = R.init_eq(pr, 0, p=rng.uniform(-0.01, 0.01, (7, 6, 5)),
+                  u=rng.uniform(-0.03, 0.03, (3, 7, 6, 5)))
+    for t in (1, 2):
+        f = R.run(pr, f, t - 1, 1)
+        u = R.macros(pr, f, t)[1]
+        assert np.max(np.abs(u[2, -1])) <= 1e-17
+        assert np.max(np.abs(u[:2, -1, 1:-1])) > 1e-4
+
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_node_symmetry_half_channel_equals_full(q):
+    """Force-driven channel between node-based velocity walls at z = 0 and
+    z = 2m: its lower half (z = 0..m) equals the half channel with a
+    node-layer symmetry face at z = m, to rounding, at every time level."""
+    m, nu, g = 6, 0.1, 1e-5
+    s = svec(q, 1.0 / (3 * nu + 0.5)) + np.linspace(-0.02, 0.02, q)
+    full = R.problem(q, 3, 4, 2 * m + 1, s, F0=(g, 0, 0),
+                     faces=("periodic",) * 4 + ("velocity", "velocity"))
+    half = R.problem(q, 3, 4, m + 1, s, F0=(g, 0, 0),
+                     faces=("periodic",) * 4 + ("velocity", "symmetry_node"))
+    ff, fh = R.init_eq(full), R.init_eq(half)
+    for t in (50, 500):
+        ff = R.run(full, ff, 0 if t == 50 else 50, t - (0 if t == 50 else 50))
+        fh = R.run(half, fh, 0 if t == 50 else 50, t - (0 if t == 50 else 50))
+        uf = R.macros(full, ff, t)[1]
+        uh = R.macros(half, fh, t)[1]
+        assert np.max(np.abs(uf[:, : m + 1] - uh)) <= 1e-13 * np.max(np.abs(uf))
+
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_node_symmetry_half_cavity_equals_full(q):
+    """Sec. 4.3 on a node-based grid (the paper's 97x97x49 layout, small):
+    cavity with node-based velocity walls, lid on +x moving along +y; the
+    half cavity with a node-layer symmetry face at mid-depth equals the
+    lower half of the full cavity, transient included."""
+    n, m = 7, 4
+    s = svec(q, 1.5) + np.linspace(-0.02, 0.02, q)
+    lid = {"+x": (0.0, 0.08, 0.0)}
+    full = R.problem(q, n, n, 2 * m + 1, s, faces=("velocity",) * 6, wall_u=lid)
+    half = R.problem(q, n, n, m + 1, s, faces=("velocity",) * 5 + ("symmetry_node",), wall_u=lid)
+    ff = R.run(full, R.init_eq(full), 0, 40)
+    fh = R.run(half, R.init_eq(half), 0, 40)
+    pf, uf = R.macros(full, ff, 40)
+    ph, uh = R.macros(half, fh, 40)
+    assert np.max(np.abs(uf[:, : m + 1] - uh)) <= 1e-13 * np.max(np.abs(uf))
+    assert np.max(np.abs(pf[: m + 1] - ph)) <= 1e-13 * max(np.max(np.abs(pf)), 1e-30)
