@@ -87,10 +87,22 @@ typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
  * x_f = x_b + the inward normals of its faces (p_f, u_f: the macroscopic
  * fields there, Eq. (hgl)).  A velocity face fixes u_b = wall_u and takes
  * p_b = p_f; a pressure face fixes p_b = face_p + face_pA cos(2 pi t / FT)
- * (FT > 0, else face_p) at the new time level and takes u_b = u_f.  At edges
- * and corners both kinds apply; among faces of one kind the z face wins,
- * then y, then x.  An axis with such a face needs at least 3 nodes.  Single
- * lattices only (batches reject them).
+ * (FT > 0, else face_p) at the new time level and takes u_b = u_f.
+ * At edges and corners both kinds apply; among faces of one kind the z
+ * face wins, then y, then x.
+ *
+ * LBM_SYMMETRY_NODE is the symmetry plane of Eq. (z05symmetry) through the
+ * last node layer (node-based grids such as the paper's 97x97x49 half
+ * cavity): after every step, the populations of a node on the plane that
+ * arrive from beyond it are set to the mirrored populations of the same
+ * node (those the layer below sent towards the plane), so a half domain
+ * evolves exactly as the lower half of the full mirror-symmetric one.  A
+ * node on both such a plane and a velocity / pressure face follows the
+ * latter, extrapolating from its inward neighbour after the plane's
+ * mirroring.
+ *
+ * Velocity, pressure and node-layer symmetry faces need at least 3 nodes on
+ * their axis, and run on single lattices only (batches reject them).
  *
  * wall_u is used on wall and velocity faces and ignored elsewhere. */
 typedef enum {
@@ -98,7 +110,8 @@ typedef enum {
   LBM_WALL = 1,
   LBM_SYMMETRY = 2,
   LBM_VELOCITY = 3,
-  LBM_PRESSURE = 4
+  LBM_PRESSURE = 4,
+  LBM_SYMMETRY_NODE = 5
 } lbm_face_kind;
 
 /* Rounding of LBM_F16DEV stores made by a time step.  Stochastic (the

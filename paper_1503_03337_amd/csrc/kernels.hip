@@ -589,20 +589,24 @@ __device__ __forceinline__ void feq_c(C p, C ux, C uy, C uz, C (&fe)[Q]) {
 // exact inverse of read_node's addressing (each physical population of
 // each node has one slot, so stores for one node never touch a slot that
 // represents another node's population).
+// Only the populations whose bit is set in `sel` are stored.
 template <int Q, int ST, int PHASE>
 __device__ __forceinline__ void store_node(const LatticeArgs<typename Codec<ST>::C>& A,
                                            typename Codec<ST>::S* dst, unsigned n, int x, int y,
-                                           int z, const typename Codec<ST>::C (&f)[Q], unsigned h) {
+                                           int z, const typename Codec<ST>::C (&f)[Q], unsigned h,
+                                           unsigned sel) {
   using C = typename Codec<ST>::C;
   using L = Lattice<Q>;
   const long long st = A.stride;
   if (PHASE == 0) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) pop_store(dst + a * st + n, enc_step<ST>(A, f[a], a, h, a));
+    for (int a = 0; a < Q; ++a)
+      if (sel & (1u << a)) pop_store(dst + a * st + n, enc_step<ST>(A, f[a], a, h, a));
   } else {
     const Nbr b = make_nbr<true>(A, x, y, z);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
+      if (!(sel & (1u << a))) continue;
       const int o = L::opp[a];
       int off, slot;
       bool wall;
@@ -614,10 +618,51 @@ __device__ __forceinline__ void store_node(const LatticeArgs<typename Codec<ST>:
   }
 }
 
-// One thread per listed boundary node x_b: inward neighbour x_f (never on a
-// velocity / pressure face itself, as each such axis has >= 3 nodes), its
-// p_f, u_f (Eq. (hgl), u = sum c f + F/2) and f_neq = f(x_f) - f_eq(p_f, u_f);
-// then f(x_b) = f_eq(p_b, u_b) + f_neq.
+// Node-layer symmetry planes: at a node on such planes, the populations that
+// arrive from beyond a plane are replaced by the mirrored populations of the
+// same node (which streaming delivered from the layer below); returns the
+// mask of replaced populations (0 if the node is on no such plane).
+template <int Q, typename C>
+__device__ __forceinline__ unsigned mirror_arrivals(const NeeArgs<C>& E, const int (&dim)[3],
+                                                    const int (&own)[3], C (&f)[Q]) {
+  using L = Lattice<Q>;
+  int side[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    side[d] = (own[d] == 0 && E.kind[2 * d] == 5) ? -1
+              : (own[d] == dim[d] - 1 && E.kind[2 * d + 1] == 5) ? 1 : 0;
+  if (!(side[0] | side[1] | side[2])) return 0u;
+  C g[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) g[a] = f[a];
+  unsigned sel = 0u;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const bool bx = L::cx[a] * side[0] < 0, by = L::cy[a] * side[1] < 0,
+               bz = L::cz[a] * side[2] < 0;
+    const C lo = by ? (bx ? g[mirror<Q>(a, 3)] : g[mirror<Q>(a, 2)])
+                    : (bx ? g[mirror<Q>(a, 1)] : g[a]);
+    const C hi = by ? (bx ? g[mirror<Q>(a, 7)] : g[mirror<Q>(a, 6)])
+                    : (bx ? g[mirror<Q>(a, 5)] : g[mirror<Q>(a, 4)]);
+    f[a] = bz ? hi : lo;
+    if (bx | by | bz) sel |= 1u << a;
+  }
+  return sel;
+}
+
+// One thread per listed boundary node x_b.  On velocity / pressure faces
+// (non-equilibrium extrapolation): inward neighbour x_f (never on such a
+// face itself, as each such axis has >= 3 nodes; if it lies on a node-layer
+// symmetry plane its arriving populations are taken mirrored, as that
+// plane's own pass defines them), its p_f, u_f (Eq. (hgl), u = sum c f +
+// F/2) and f_neq = f(x_f) - f_eq(p_f, u_f); then f(x_b) = f_eq(p_b, u_b) +
+// f_neq.  Otherwise, on node-layer symmetry planes only: the arriving
+// populations become the mirrored ones.  Each thread writes only its own
+// node's populations.  It reads its own node, or an inward neighbour on no
+// velocity / pressure face; if that neighbour is on a symmetry plane, its
+// arrival slots (which the neighbour's own thread may be rewriting) are
+// read but not used, the mirrored values standing in for them exactly as
+// the owner computes them, so the result does not depend on thread order.
 template <int Q, int ST, int PHASE>
 __global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> A,
                                              NeeArgs<typename Codec<ST>::C> E,
@@ -625,19 +670,21 @@ __global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> 
   using CD = Codec<ST>;
   using C = typename CD::C;
   using L = Lattice<Q>;
+  const int dim[3] = {A.nx, A.ny, A.nz};
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const unsigned n = (unsigned)nodes[i];
     int x, y, z;
     node_xyz(n, A.nx, A.ny, x, y, z);
-    const int own[3] = {x, y, z}, dim[3] = {A.nx, A.ny, A.nz};
+    const int own[3] = {x, y, z};
     int src[3] = {x, y, z}, vf = -1, pf = -1;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int face = -1;
-      if (own[d] == 0 && (E.kind[2 * d] == 3 || E.kind[2 * d] == 4)) {
+      const int klo = E.kind[2 * d], khi = E.kind[2 * d + 1];
+      if (own[d] == 0 && (klo == 3 || klo == 4)) {
         face = 2 * d;
         src[d] = 1;
-      } else if (own[d] == dim[d] - 1 && (E.kind[2 * d + 1] == 3 || E.kind[2 * d + 1] == 4)) {
+      } else if (own[d] == dim[d] - 1 && (khi == 3 || khi == 4)) {
         face = 2 * d + 1;
         src[d] = dim[d] - 2;
       }
@@ -647,10 +694,20 @@ __global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> 
       else
         pf = face;
     }
+    const unsigned h = node_hash(n, A.tstep) ^ 0x68E31DA4u;
+    if (vf < 0 && pf < 0) {
+      // node-layer symmetry planes only
+      C f[Q];
+      read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), n, x, y, z, f);
+      const unsigned sel = mirror_arrivals<Q, C>(E, dim, own, f);
+      store_node<Q, ST, PHASE>(A, static_cast<typename CD::S*>(A.f), n, x, y, z, f, h, sel);
+      continue;
+    }
     const unsigned m = (unsigned)src[0] + (unsigned)A.nx * ((unsigned)src[1] + (unsigned)A.ny * (unsigned)src[2]);
     C ff[Q];
     read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), m, src[0], src[1],
                                   src[2], ff);
+    (void)mirror_arrivals<Q, C>(E, dim, src, ff);
     C P = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
@@ -674,8 +731,8 @@ __global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> 
     feq_c<Q, C>(pb, bx, by, bz, fb);
 #pragma unroll
     for (int a = 0; a < Q; ++a) fb[a] += ff[a] - fe[a];
-    store_node<Q, ST, PHASE>(A, static_cast<typename CD::S*>(A.f), n, x, y, z, fb,
-                             node_hash(n, A.tstep) ^ 0x68E31DA4u);
+    store_node<Q, ST, PHASE>(A, static_cast<typename CD::S*>(A.f), n, x, y, z, fb, h,
+                             (1u << Q) - 1u);
   }
 }
 

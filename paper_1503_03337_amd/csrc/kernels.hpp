@@ -56,7 +56,8 @@ template <typename C> struct LatticeArgs {
 // Boundary values of the velocity / pressure faces (non-equilibrium
 // extrapolation) at the time level being completed.
 template <typename C> struct NeeArgs {
-  int kind[6];   // 3 velocity face, 4 pressure face, anything else: neither
+  int kind[6];   // 3 velocity face, 4 pressure face, 5 node-layer symmetry
+                 // face, anything else: none of these
   C u[6][3];     // velocity of a velocity face
   C p[6];        // pressure of a pressure face at this level
 };

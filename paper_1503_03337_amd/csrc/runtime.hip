@@ -50,7 +50,9 @@ size_t population_bytes(int q, size_t N, int storage) {
   return (size_t)q * pop_stride(N) * (size_t)bytes_of(storage);
 }
 
-bool is_nee_face(int kind) { return kind == LBM_VELOCITY || kind == LBM_PRESSURE; }
+bool is_nee_face(int kind) {
+  return kind == LBM_VELOCITY || kind == LBM_PRESSURE || kind == LBM_SYMMETRY_NODE;
+}
 
 // Number of nodes on velocity / pressure faces: all nodes minus the box of
 // nodes on none of them.
@@ -86,13 +88,14 @@ std::string validate(int model, int nx, int ny, int nz, const double* s, const l
   }
   for (int d = 0; d < 3; ++d) {
     const int a = sp->face[2 * d], b = sp->face[2 * d + 1];
-    if (a < LBM_PERIODIC || a > LBM_PRESSURE || b < LBM_PERIODIC || b > LBM_PRESSURE)
-      return "face kind must be LBM_PERIODIC, LBM_WALL, LBM_SYMMETRY, LBM_VELOCITY or "
-             "LBM_PRESSURE";
+    if (a < LBM_PERIODIC || a > LBM_SYMMETRY_NODE || b < LBM_PERIODIC || b > LBM_SYMMETRY_NODE)
+      return "face kind must be LBM_PERIODIC, LBM_WALL, LBM_SYMMETRY, LBM_VELOCITY, "
+             "LBM_PRESSURE or LBM_SYMMETRY_NODE";
     if ((a == LBM_PERIODIC) != (b == LBM_PERIODIC)) return "periodic faces must come in pairs";
     const int dim[3] = {nx, ny, nz};
     if ((is_nee_face(a) || is_nee_face(b)) && dim[d] < 3)
-      return "an axis with a velocity or pressure face needs at least 3 nodes";
+      return "an axis with a velocity, pressure or node-layer symmetry face needs at least 3 "
+             "nodes";
   }
   for (int f = 0; f < 6; ++f)
     if (!std::isfinite(sp->face_p[f]) || !std::isfinite(sp->face_pA[f]))

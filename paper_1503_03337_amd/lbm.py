@@ -24,7 +24,8 @@ STORAGE = {"f64": 0, "f32": 1, "f16dev": 2}
 ROUNDING = {"stochastic": 0, "nearest": 1}
 COLLISION = {"mrt": 0, "bgk": 1}
 PATTERN = {"ab": 0, "aa": 1}
-FACE_KIND = {"periodic": 0, "wall": 1, "symmetry": 2, "velocity": 3, "pressure": 4}
+FACE_KIND = {"periodic": 0, "wall": 1, "symmetry": 2, "velocity": 3, "pressure": 4,
+             "symmetry_node": 5}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
 

@@ -59,7 +59,7 @@ def test_footprint_without_device():
     dict(model=15), dict(nx=0), dict(faces=("periodic", "wall") + ("wall",) * 4),
     dict(wall_u={"+z": (0.3, 0, 0)}), dict(storage=7), dict(pattern=5),
     dict(storage="f16dev", f16_scale_log2=30), dict(monitor_every=-1),
-    dict(faces=("periodic", "symmetry") + ("wall",) * 4), dict(faces=(5,) + ("wall",) * 5),
+    dict(faces=("periodic", "symmetry") + ("wall",) * 4), dict(faces=(6,) + ("wall",) * 5),
     dict(faces=("wall",) * 5 + (-1,)),
     dict(nx=2, faces=("pressure", "pressure") + ("velocity",) * 4),
     dict(faces=("pressure", "wall") + ("wall",) * 4, face_p={"-x": float("nan")}),

@@ -240,3 +240,50 @@ def test_large_class_two_tiles_per_workgroup_bit_exact():
     for k, lat in enumerate(lats):
         assert np.array_equal(lat.macros()[1], alone[k]), k
         lat.close()
+
+
+def test_cavity_batch_256_full_size():
+    """The 256-cavity batch (edge U{24..96}, Re U[100,1000], D3Q14/D3Q18,
+    FP32, seed 0) in the launch configuration the benchmark times (one
+    launch per class and step, the large classes two tiles per workgroup):
+    the five smallest members match the FP64 oracle after 6 steps from a
+    random state (FP32 tolerance), and every member conserves its mass (the
+    lids are tangential) to FP32 rounding."""
+    from paper_1503_03337_amd import params
+    spec = inputs.cavity_batch(256, seed=0)
+    lats = []
+    for k, c in enumerate(spec):
+        L = c["edge"]
+        cfg = params.cavity(c["q"], L, c["Re"], lid=c["lid"])
+        lat = lbm.Lattice(c["q"], L, L, L, cfg["s_vec"], faces=cfg["faces"],
+                          wall_u=cfg["wall_u"], storage="f32", pattern="aa")
+        lats.append((lat, cfg))
+    b = lbm.Batch(lats[0][0].stream)
+    small = sorted(range(len(spec)), key=lambda k: spec[k]["edge"])[:5]
+    start = {}
+    for k, (lat, cfg) in enumerate(lats):
+        if k in small:
+            L = spec[k]["edge"]
+            lat.set_f(inputs.random_populations(cfg["model"], L, L, L, seed=900 + k))
+            start[k] = lat.get_f()
+        b.add(lat, 6)
+    mass0 = [float(np.sum(lat.get_f(), dtype=np.float64)) for lat, _ in lats]
+    b.step(6)
+    b.close()
+    for k, (lat, cfg) in enumerate(lats):
+        assert lat.time == 6
+        f = lat.get_f()
+        m = float(np.sum(f, dtype=np.float64))
+        # (members started at rest have p0 = 0, all populations 0: the
+        # scale is the populations' magnitude, not the mass)
+        assert abs(m - mass0[k]) <= 1e-6 * float(np.sum(np.abs(f))), (k, m, mass0[k])
+        if k in small:
+            L = spec[k]["edge"]
+            pr = R.problem(cfg["model"], L, L, L, cfg["s_vec"], faces=cfg["faces"],
+                           wall_u=cfg["wall_u"])
+            ref = R.run(pr, start[k], 0, 6)
+            _, u = lat.macros()
+            _, ur = R.macros(pr, ref, 6)
+            assert np.linalg.norm(u - ur) <= 1e-5 * np.linalg.norm(ur), k
+    for lat, _ in lats:
+        lat.close()

@@ -1,5 +1,6 @@
-"""Velocity / pressure faces (non-equilibrium extrapolation, the boundary
-scheme of the paper's Sec. 4) on the GPU, through the C ABI:
+"""Node-based faces on the GPU, through the C ABI: velocity / pressure faces
+(non-equilibrium extrapolation, the boundary scheme of the paper's Sec. 4)
+and node-layer symmetry planes (Eq. (z05symmetry) on the node-based grid):
 
 * element-wise against the FP64 oracle on random states, every step of
   both AA parities and AB, with time-dependent face pressure, a moving
@@ -7,6 +8,8 @@ scheme of the paper's Sec. 4) on the GPU, through the C ABI:
   periodic axes (FP64 1e-13 of max|f|; FP32 / FP16 at their storage
   tolerances);
 * AA == AB bit for bit;
+* the 49 x 49 x 25 half cavity with a node-layer symmetry plane equals the
+  lower half of the full 49^3 cavity;
 * the paper's own numbers: every entry of Table 1 (steady Poiseuille,
   Sec. 4.1, dx = 1/8 .. 1/64, 1/tau = 0.8, 1.0, 1.3) and Table 2
   (pulsatile, Sec. 4.2, dx = 1/20 .. 1/80, four phases) to the last
@@ -36,6 +39,13 @@ SETUPS = {
                 {"+x": 0.001, "-y": -0.002, "+z": 0.003}, None, (0, 0, 0), 0.0),
     "long": ((300, 3, 4), ("pressure", "pressure", "periodic", "periodic", "velocity", "velocity"),
              None, {"-x": 0.003, "+x": 0.0}, None, (0, 0, 0), 0.0),
+    # node-layer symmetry planes: a half cavity (lid +x along +y), and two
+    # planes meeting at an edge beside a pressure face and a half-way wall
+    "halfcavity_node": ((9, 8, 6), ("velocity",) * 5 + ("symmetry_node",),
+                        {"+x": (0.0, 0.08, 0.0)}, None, None, (0, 0, 0), 0.0),
+    "symnode_edges": ((10, 7, 6), ("pressure", "symmetry_node", "wall", "symmetry_node",
+                                   "periodic", "periodic"),
+                      {"-y": (0.03, 0.0, 0.0)}, {"-x": 0.002}, None, (1e-5, 0.0, 0.0), 0.0),
 }
 
 
@@ -172,3 +182,27 @@ def test_table2_pulsatile_reproduced(k, inv):
         print("GPU Table 2, dx=1/%d %s: GRE %.5e printed %.3e" % (inv, name, gre, p))
     for name, gre, p in out:
         assert within_last_digit(gre, p), (name, gre, p)
+
+
+def test_half_cavity_node_symmetry_equals_full_cavity():
+    """Sec. 4.3 on its own node-based grid (49 x 49 x 25, Re = 1000 at lid
+    speed 0.1, iD3Q14 FP64): the half cavity with a node-layer symmetry
+    plane equals the lower half of the full 49^3 cavity after 3000 steps.
+    The lid is the +x face moving along +y, so that under the z > y > x
+    rule its edges belong to the resting walls."""
+    q, n, steps = 14, 49, 3000
+    nu = 1e-3 / (10.0 / (n - 1))
+    s = svec(q, 1.0 / (3 * nu + 0.5))
+    lid = {"+x": (0.0, 0.1, 0.0)}
+    full = lbm.Lattice(q, n, n, n, s, faces=("velocity",) * 6, wall_u=lid, storage="f64")
+    half = lbm.Lattice(q, n, n, (n + 1) // 2, s, faces=("velocity",) * 5 + ("symmetry_node",),
+                       wall_u=lid, storage="f64")
+    full.step(steps)
+    half.step(steps)
+    uf = full.macros()[1]
+    uh = half.macros()[1]
+    full.close()
+    half.close()
+    err = np.max(np.abs(uf[:, : (n + 1) // 2] - uh)) / np.max(np.abs(uf))
+    print("node-layer half cavity 49x49x25 vs full 49^3: max rel diff %.2e" % err)
+    assert err <= 1e-12
