@@ -257,8 +257,10 @@ int lbm_destroy(lbm_ctx* ctx);
 int lbm_batch_create(lbm_batch** out, void* stream);
 int lbm_batch_add(lbm_batch* b, lbm_ctx* ctx, long long step_budget);
 int lbm_batch_remove(lbm_batch* b, lbm_ctx* ctx);
-/* Tile of a member: tx*ty <= 256 nodes of one x-y plane per workgroup
- * (0,0 = automatic). */
+/* Mapping of a member's nodes to workgroups: a tx x ty tile (tx*ty <= 256
+ * nodes of one x-y plane), or (0,0) = automatic: 256 consecutive nodes in
+ * linear order (every wavefront full and aligned whatever nx; members with
+ * N >= 2^30 nodes use a row tile instead).  Results do not depend on it. */
 int lbm_batch_set_tile(lbm_batch* b, lbm_ctx* ctx, int tx, int ty);
 int lbm_batch_step(lbm_batch* b, long long n);
 /* Run the monitor of every member created with monitor_every > 0 (one

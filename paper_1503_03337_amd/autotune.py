@@ -1,12 +1,14 @@
 """Tile-shape autotuner for batched execution.
 
-A workgroup of the batched kernel covers a tx x ty tile of one x-y plane of
-its member (tx * ty <= 256 threads).  The best shape depends on the edge
-length (full rows keep each wavefront on contiguous memory; short rows
-waste lanes unless several rows share a workgroup) and on q.  For every
-(q, edge bucket) present in a batch the tuner times each candidate tile on a
-small batch of that bucket's members and keeps the fastest.  The tile never
-changes results (each node's arithmetic is the same), only speed.
+A workgroup of the batched kernel covers either 256 consecutive nodes of
+its member (the automatic "flat" mapping, tile (0, 0): every wavefront full
+and aligned whatever the edge) or a tx x ty tile of one x-y plane (tx * ty
+<= 256 threads).  The best choice depends on the edge length and on q.  For
+every (q, edge bucket) present in a batch the tuner times each candidate on
+a batch of copies of that bucket's median member, large enough (>= 2^22
+nodes) to run from HBM as the real batch does, and keeps the fastest.  The
+mapping never changes results (each node's arithmetic is the same), only
+speed.
 """
 import time
 
@@ -14,8 +16,8 @@ from . import lbm
 
 
 def candidates(edge):
-    """Tile shapes worth trying for rows of `edge` nodes."""
-    out = []
+    """Mappings worth trying for rows of `edge` nodes: flat, then tiles."""
+    out = [(0, 0)]
     if edge <= 256:
         out.append((edge, max(1, min(edge, 256 // edge))))
     for tx in (256, 128, 64, 32, 16):
@@ -33,10 +35,10 @@ def bucket(edge, width=8):
     return (edge // width) * width
 
 
-def tune(make_lattice, keys, steps=40, reps=2, stream=None, sync=None):
+def tune(make_lattice, keys, steps=40, reps=2, stream=None, sync=None, min_nodes=1 << 22):
     """keys: iterable of (q, edge).  make_lattice(q, edge) returns a fresh
     lbm.Lattice (FP32 or FP16DEV, AA).  Returns {(q, bucket(edge)): (tx, ty)}
-    and the measured MLUPS per candidate."""
+    ((0, 0): the flat mapping) and the measured MLUPS per candidate."""
     import torch
     best, log = {}, {}
     groups = {}
@@ -44,7 +46,8 @@ def tune(make_lattice, keys, steps=40, reps=2, stream=None, sync=None):
         groups.setdefault((q, bucket(edge)), []).append(edge)
     for (q, bk), edges in sorted(groups.items()):
         sample = sorted(edges)[len(edges) // 2]
-        lats = [make_lattice(q, sample) for _ in range(4)]
+        copies = max(2, -(-min_nodes // sample ** 3))
+        lats = [make_lattice(q, sample) for _ in range(copies)]
         nodes = sum(l.N for l in lats)
         results = {}
         for tile in candidates(sample):

@@ -1005,17 +1005,29 @@ template <int Q, int ST, int MODE, bool FORCED>
 __device__ __forceinline__ void batch_tile(const BatchMember& m, const float* __restrict__ ftab,
                                            int own, unsigned lt) {
   LatticeArgs<float> A = m.a;
-  const int tx = A.tx;
   const unsigned t = threadIdx.x;
-  if (t >= (unsigned)(tx * A.ty)) return;
-  const unsigned r = fast_div(lt, A.fd_tiles_x);
-  const int bx = (int)(lt - r * (unsigned)A.tiles_x);
-  const unsigned zz = fast_div(r, A.fd_tiles_y);
-  const int by = (int)(r - zz * (unsigned)A.tiles_y);
-  const unsigned ly = fast_div(t, A.fd_tx);
-  const int x = bx * tx + (int)(t - ly * (unsigned)tx);
-  const int y = by * A.ty + (int)ly;
-  if (x >= A.nx || y >= A.ny) return;
+  int x, y;
+  unsigned zz;
+  if (m.flat) {
+    // 256 consecutive nodes (every wavefront full and aligned, whatever nx)
+    const unsigned n = lt * 256u + t;
+    if (n >= (unsigned)A.nx * (unsigned)A.ny * (unsigned)A.nz) return;
+    const unsigned r = fast_div(n, m.fd_nx);
+    x = (int)(n - r * (unsigned)A.nx);
+    zz = fast_div(r, m.fd_ny);
+    y = (int)(r - zz * (unsigned)A.ny);
+  } else {
+    const int tx = A.tx;
+    if (t >= (unsigned)(tx * A.ty)) return;
+    const unsigned r = fast_div(lt, A.fd_tiles_x);
+    const int bx = (int)(lt - r * (unsigned)A.tiles_x);
+    zz = fast_div(r, A.fd_tiles_y);
+    const int by = (int)(r - zz * (unsigned)A.tiles_y);
+    const unsigned ly = fast_div(t, A.fd_tx);
+    x = bx * tx + (int)(t - ly * (unsigned)tx);
+    y = by * A.ty + (int)ly;
+    if (x >= A.nx || y >= A.ny) return;
+  }
   A.tstep += (unsigned)own;
   if (FORCED) {
     if (m.forced) {

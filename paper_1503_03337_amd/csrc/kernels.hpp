@@ -111,6 +111,8 @@ struct BatchMember {
   long long ntiles;
   long long ftab_off;      // float offset of this member's F(t) rows (3 per own step)
   int forced;
+  int flat;                // 1: tile lt = nodes [256 lt, 256 lt + 256) in linear order
+  FastDiv fd_nx, fd_ny;    // flat tiles: node index -> (x, y, z)
 };
 // Tiles of one member run one after the other by one workgroup of a large
 // batched launch.

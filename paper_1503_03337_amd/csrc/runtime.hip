@@ -715,6 +715,13 @@ struct Member {
   long long remaining;
   int tx, ty;  // 0: automatic
 };
+
+// Automatic mapping of a member's nodes to workgroups: 256 consecutive
+// nodes each ("flat"; measured 2-5 % faster than row tiles for edges that
+// are not multiples of 64, equal at 64), or tiles of whole rows for members
+// with N >= 2^30 (the flat node index is decoded with multiply-shift
+// division, exact below 2^30).
+bool member_flat(const Member& m) { return m.tx == 0 && m.ctx->N < (1u << 30); }
 }  // namespace
 
 // Launch classes of at least this many tiles (2^22 nodes at 256 nodes a
@@ -881,6 +888,7 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   // grouped by class
   auto member_tiles = [&](int i) {
     const lbm_ctx* c = b->members[i].ctx;
+    if (member_flat(b->members[i])) return (long long)((c->N + 255) / 256);
     int tx = b->members[i].tx, ty = b->members[i].ty;
     if (tx == 0) pick_tile(c->nx, c->ny, tx, ty);
     return (long long)((c->nx + tx - 1) / tx) * ((c->ny + ty - 1) / ty) * c->nz;
@@ -932,6 +940,12 @@ int lbm_batch_step(lbm_batch* b, long long n) {
     bm.steps = (int)k;
     bm.tile_begin = tiles;
     bm.ntiles = (long long)bm.a.tiles_x * bm.a.tiles_y * c->nz;
+    bm.flat = member_flat(m) ? 1 : 0;
+    if (bm.flat) {
+      bm.ntiles = (long long)((c->N + 255) / 256);
+      bm.fd_nx = make_fastdiv((unsigned)c->nx);
+      bm.fd_ny = make_fastdiv((unsigned)c->ny);
+    }
     tiles += bm.ntiles;
     if (cls_big[k_cls])
       for (long long t0 = 0; t0 < bm.ntiles; t0 += kBatchChunk) {

@@ -127,6 +127,7 @@ def test_continuous_admission_and_retirement():
 
 @pytest.mark.parametrize("tile", [(16, 16), (64, 4), (32, 8), (7, 9), (1, 1)])
 def test_tile_shape_does_not_change_results(tile):
+    """Row tiles of any shape give the automatic (flat) mapping's result."""
     ref = run_alone(2, 5, 500)
     lat = build(2, 500)
     b = lbm.Batch(lat.stream)
@@ -212,7 +213,8 @@ def test_large_class_two_tiles_per_workgroup_bit_exact():
     member still equals its alone run (one tile per workgroup) bit for bit,
     including a ragged last chunk (odd tile counts)."""
     q, steps = 18, 5
-    dims = [(112, 112, 112), (112, 113, 113), (112, 112, 111)]  # 6272 + 6441 + 6216 tiles
+    # 256-node tiles of the automatic mapping: 5488 + 5586 + 5439 = 16513
+    dims = [(112, 112, 112), (112, 113, 113), (112, 112, 111)]
     s = svec(q, 1.6) + np.linspace(-0.02, 0.02, q)
 
     def make(k):
