@@ -395,3 +395,52 @@ def test_bgk_matches_oracle(q, storage, pattern, setup):
         _, ur = R.macros(pr, ref, 3)
         assert rel_l2(u, ur) <= 1e-5
     lat.close()
+
+
+DEGENERATE = [(1, 1, 1), (1, 5, 4), (6, 1, 3), (5, 4, 1), (2, 2, 2), (257, 1, 2), (3, 2, 300)]
+DEGENERATE_FACES = {
+    "periodic": ("periodic",) * 6,
+    "walls": ("wall",) * 6,
+    "mixed": ("wall", "symmetry", "periodic", "periodic", "symmetry", "wall"),
+}
+
+
+@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("faces", sorted(DEGENERATE_FACES))
+@pytest.mark.parametrize("dims", DEGENERATE, ids=lambda d: "x".join(map(str, d)))
+def test_degenerate_shapes_match_oracle(q, pattern, faces, dims):
+    """Axes of one or two nodes (every link of the axis wraps onto, bounces
+    at or mirrors into the node itself), rows longer than one 256-wide tile,
+    long z: FP64 element-wise against the oracle for three steps (both AA
+    parities), with a moving wall and a body force."""
+    fs = DEGENERATE_FACES[faces]
+    wall_u = {"+z": (0.05, 0.02, 0.0), "-x": (0.0, 0.03, 0.01)}
+    F0 = (2e-5, -1e-5, 1e-5)
+    lat = lbm.Lattice(q, *dims, rates(q), faces=fs, wall_u=wall_u, F0=F0, storage="f64",
+                      pattern=pattern)
+    pr = R.problem(q, *dims, rates(q), faces=fs, wall_u=wall_u, F0=F0)
+    lat.set_f(inputs.random_populations(q, *dims, seed=21))
+    f = lat.get_f()
+    scale = np.max(np.abs(f))
+    for t in range(1, 4):
+        lat.step(1)
+        f = R.run(pr, f, t - 1, 1)
+        assert np.max(np.abs(lat.get_f() - f)) <= 1e-13 * scale, t
+    lat.close()
+
+
+def test_zero_steps_change_nothing():
+    q = 18
+    lat = lbm.Lattice(q, 9, 8, 7, rates(q), faces=FACESETS["cavity"], storage="f32")
+    lat.set_f(inputs.random_populations(q, 9, 8, 7, seed=22))
+    f0 = lat.get_f()
+    lat.step(0)
+    assert lat.time == 0 and np.array_equal(lat.get_f(), f0)
+    b = lbm.Batch(lat.stream)
+    b.step(5)  # an empty batch does nothing
+    b.add(lat, 3)
+    b.step(0)
+    assert lat.time == 0 and np.array_equal(lat.get_f(), f0)
+    b.close()
+    lat.close()
