@@ -32,5 +32,24 @@ def build(verbose=False, extra=()):
     return LIB
 
 
+C_ABI_TEST = os.path.join(os.path.dirname(HERE), "tests", "c_abi")
+
+
+def build_c_abi_test(verbose=False):
+    """The plain-C program that drives the library through include/lbm.h
+    only (tests/c_abi/lid_cavity.c), linked against liblbm.so with a
+    relative run path."""
+    src = os.path.join(C_ABI_TEST, "lid_cavity.c")
+    out = os.path.join(C_ABI_TEST, "lid_cavity")
+    rel = os.path.relpath(HERE, C_ABI_TEST)
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", src, "-o", out + ".tmp", "-L" + HERE,
+           "-llbm", "-Wl,-rpath,$ORIGIN/" + rel]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True, extra=sys.argv[1:])

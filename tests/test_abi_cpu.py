@@ -133,3 +133,16 @@ def test_footprint_holds_the_boundary_node_list():
     nee = lbm.footprint_bytes(14, 17, 9, 9, faces=faces, storage="f64")
     count = 17 * 9 * 9 - 15 * 7 * 7
     assert nee - walls == (4 * count + 255) // 256 * 256
+
+
+def test_plain_c_program_links_and_validates():
+    """tests/c_abi/lid_cavity.c uses nothing but include/lbm.h and
+    liblbm.so (no Python, no torch); its validation-only mode makes no
+    device call."""
+    import os
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c_abi", "lid_cavity")
+    assert os.path.exists(exe), "build it with __graft_entry__.build()"
+    out = subprocess.run([exe, "--check-only"], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    assert "validation ok" in out.stdout
