@@ -84,7 +84,8 @@ def paper_poiseuille(dx, inv_tau, nu_phys=0.03, p_in=1.1, p_out=1.0):
 
 def paper_pulsatile(dx, tau=0.6178, period=100.0, dp=1e-3, p_out=1.0):
     """Sec. 4.2 convergence study: c = 1 at dx = 1/20 and doubling as dx
-    halves (tau, nu fixed), dp/dx = G cos(omega t), G = dp / l."""
+    halves (tau, nu fixed), dp/dx = G cos(omega t), G = dp / l.  Table 3 is
+    the dx = 1/20 case with tau = 0.9 and dp from 1e-3 to 5e-2."""
     c = (1.0 / dx) / 20.0
     dt = dx / c
     nu_phys = c * c * (tau - 0.5) * dt / 3.0
@@ -113,7 +114,8 @@ def paper_gre(u_lat, c, ua_phys):
 
 
 def printed_table(table):
-    """{row label: [values at the four grid spacings]} of Table 1 / 2."""
+    """{row label: [printed values]} of Table 1 / 2 (the four grid spacings)
+    or Table 3 (d'Humieres D3Q15, iD3Q14)."""
     out = {}
     for rec in read_records("paper_gre_tables.txt"):
         if rec[0] == table:

@@ -206,3 +206,28 @@ def test_half_cavity_node_symmetry_equals_full_cavity():
     err = np.max(np.abs(uf[:, : (n + 1) // 2] - uh)) / np.max(np.abs(uf))
     print("node-layer half cavity 49x49x25 vs full 49^3: max rel diff %.2e" % err)
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("dp", ("0.001", "0.005", "0.01", "0.02", "0.05"))
+def test_table3_id3q14_column_reproduced(dp):
+    """Table 3, iD3Q14 column (pulsatile, 41 x 21 x 21, dt = 0.05, c = 1,
+    tau = 0.9, GRE_u at t = T after four periods from rest) to the printed
+    two digits, across Ma_max = 0.0096 .. 0.48."""
+    q = 14
+    S = paper_pulsatile(1 / 20, tau=0.9, dp=float(dp))
+    nx, ny, nz, c, per = S["nx"], S["ny"], S["nz"], S["c"], S["steps_per_period"]
+    lat = lbm.Lattice(q, nx, ny, nz, svec(q, S["s_nu"]), faces=NEE_FACES, face_p=S["face_p"],
+                      face_pA=S["face_pA"], FT=float(per), storage="f64", pattern="aa")
+    lat.init_fields(np.full((nz, ny, nx), S["p_init"]), np.zeros((3, nz, ny, nx)))
+    lat.step(5 * per)
+    u = lat.macros()[1]
+    lat.close()
+    y = node_positions(ny)
+    Y, Z = np.meshgrid(y, y, indexing="xy")
+    ua = A.duct_pulsatile(Y, Z, 5 * per * S["dt"], 0.5, 0.5, -S["G"], S["nu_phys"], S["omega"],
+                          2000)
+    ua[0, :] = ua[-1, :] = ua[:, 0] = ua[:, -1] = 0.0
+    gre = paper_gre(u, c, ua)
+    printed = printed_table("table3")[dp][1]
+    print("GPU Table 3, dp=%s, iD3Q14: GRE %.5f printed %.4f" % (dp, gre, printed))
+    assert within_last_digit(gre, printed, digits=2)
