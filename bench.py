@@ -133,10 +133,28 @@ def mrt_vs_lbgk(torch, lbm, params, n=128, steps=2000):
     for coll, s in (("mrt", cfg["s_vec"]), ("lbgk", [1.0 / tau] * 18)):
         lat = lbm.Lattice(18, n, n, n, s, faces=cfg["faces"], wall_u=cfg["wall_u"],
                           storage="f32", pattern="aa", collision="bgk" if coll == "lbgk" else "mrt")
-        lat.step(100)
+        lat.step(1000)  # past the all-zero start (in-cache streaming depends on the data)
         wall, _ = time_steps(torch, lat, steps)
         lat.close()
         out[coll + "_MLUPS"] = round(n ** 3 * steps / wall / 1e6, 1)
+    return out
+
+
+def storage_variants(torch, lbm, params, n=128, steps=2000):
+    """The headline cavity (128^3 D3Q18, AA, MRT) stored as FP16 deviations
+    (72 B per node and step) and as FP64 (288 B): MLUPS and algorithmic
+    GB/s of each."""
+    cfg = params.cavity(18, n, 1000.0, lid=0.1)
+    out = {}
+    for storage, b in (("f16dev", 2), ("f64", 8)):
+        lat = lbm.Lattice(18, n, n, n, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"],
+                          storage=storage, pattern="aa")
+        lat.step(1000)
+        wall, _ = time_steps(torch, lat, steps)
+        lat.close()
+        mlups = n ** 3 * steps / wall / 1e6
+        out[storage] = {"MLUPS": round(mlups, 1),
+                        "algorithmic_GBs": round(mlups * 1e6 * 2 * 18 * b / 1e9, 1)}
     return out
 
 
@@ -205,6 +223,7 @@ def main():
     copy_gbs = copy_bandwidth(torch, lbm)
     b256 = batch256(torch, lbm, params)
     collisions = mrt_vs_lbgk(torch, lbm, params)
+    storages = storage_variants(torch, lbm, params)
 
     out = {
         "metric": METRIC,
@@ -231,6 +250,7 @@ def main():
         "copy_probe_GBs": round(copy_gbs, 1),
         "batch256": b256,
         "collision_cost": collisions,
+        "storage_variants": storages,
     }
     if not args.no_serving:
         from paper_1503_03337_amd import serve
