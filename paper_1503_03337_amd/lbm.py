@@ -208,6 +208,7 @@ class Lattice:
         if need == 0:
             raise LbmError(-1, "invalid lattice description")
         tstream, self._buf = _torch_stream_and_buffer(need, use_torch)
+        self._buf_stream = tstream  # stream torch allocated the buffer on
         if stream is None:
             stream = tstream
         sp.stream = stream
@@ -295,7 +296,13 @@ class Lattice:
                                         None if uu is None else _dptr(uu)), "lbm_init_fields")
 
     def close(self):
+        """Destroy the context.  The population buffer (a torch tensor) is
+        released to torch's caching allocator, which orders its reuse after
+        the work already queued on the stream it was allocated on; when the
+        lattice ran on another stream, that stream is drained first."""
         if getattr(self, "h", None):
+            if self._buf is not None and self.stream != self._buf_stream:
+                lib().lbm_sync(self.h)
             lib().lbm_destroy(self.h)
             self.h = None
             self._buf = None
