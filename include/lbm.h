@@ -162,11 +162,13 @@ typedef struct {
   size_t dev_buf_bytes; /* ... and its size (>= lbm_footprint_bytes)         */
   double face_p[6];     /* pressure of each LBM_PRESSURE face ...            */
   double face_pA[6];    /* ... plus face_pA cos(2 pi t / FT) when FT > 0     */
+  int graphs;           /* 1 (default): lbm_step replays captured HIP graphs
+                           where it can (see lbm_step); 0: never           */
 } lbm_spec;
 
 /* Defaults: all six faces walls at rest, no force, p0 = 0, u0 = 0, FP32,
  * AA pattern, f16_scale_log2 = 12, stochastic FP16 rounding, MRT collision,
- * no monitor, null stream, own memory. */
+ * no monitor, null stream, own memory, graphs on. */
 void lbm_spec_default(lbm_spec* spec);
 
 /* Device bytes a context of this shape needs (populations, the list of
@@ -180,8 +182,21 @@ size_t lbm_footprint_bytes(int model, int nx, int ny, int nz, const lbm_spec* sp
 int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz,
                const double* s_vec, const lbm_spec* spec);
 
-/* Advance n >= 0 time steps (one kernel launch per step, queued on the
- * context stream; returns without waiting). */
+/* Advance n >= 0 time steps (one kernel launch per step, plus one for
+ * velocity / pressure / node-layer symmetry faces, queued on the context
+ * stream; returns without waiting).
+ *
+ * With spec.graphs = 1 the launches of 32 consecutive steps are captured
+ * once into a HIP graph and replayed, which removes the per-launch host cost
+ * that dominates small lattices.  This happens when the kernel arguments do
+ * not change from step to step: a stream the caller is not capturing, no
+ * time-dependent force or face pressure (FT <= 0), and not LBM_F16DEV with
+ * stochastic rounding (its rounding bits depend on t).  The graph is
+ * recorded on a private stream of the context (the null stream cannot be
+ * captured) and launched on the context stream.  A
+ * graph never spans a monitor step.  Results are bit-identical either way.
+ * The first such call on a context captures (and keeps, until lbm_destroy)
+ * up to two graphs, one per AA parity or A/B buffer order. */
 int lbm_step(lbm_ctx* ctx, long long n);
 
 /* Pressure p[N] and velocity u[3][N] (host, FP64) at the current time level
@@ -230,6 +245,7 @@ typedef struct {
   size_t population_bytes;  /* bytes of one population copy (q*N*elem)      */
   size_t footprint_bytes;   /* everything the context holds on the device   */
   int bytes_per_value;      /* 8, 4 or 2                                    */
+  int graphs;               /* HIP graphs lbm_step has captured (0..2)      */
 } lbm_info_t;
 int lbm_info(const lbm_ctx* ctx, lbm_info_t* info);
 

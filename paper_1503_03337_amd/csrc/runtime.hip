@@ -177,6 +177,10 @@ struct lbm_ctx {
   int nee_count = 0;
   NeeArgs<double> e64{};
   NeeArgs<float> e32{};
+  // HIP graphs of kGraphSteps steps, by AA parity / A-B buffer order
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;  // where the graphs are recorded (not run)
+  bool graph_failed = false;  // a capture failed once: step eagerly from then on
   std::string err;
   void* batch = nullptr;  // batch this context belongs to (or NULL)
 };
@@ -346,6 +350,7 @@ void lbm_spec_default(lbm_spec* sp) {
   sp->storage = LBM_F32;
   sp->pattern = LBM_AA;
   sp->f16_scale_log2 = 12;
+  sp->graphs = 1;
 }
 
 size_t lbm_footprint_bytes(int model, int nx, int ny, int nz, const lbm_spec* sp) {
@@ -482,47 +487,144 @@ int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz, const double* s
   return LBM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Steps per captured graph (even, so that the AA parity and the A/B buffer
+// order are back where they started).
+constexpr int kGraphSteps = 32;
+
+// One time step of the context: the step kernel, the velocity / pressure /
+// symmetry-node pass, and the state that goes with them (no monitor).
+int eager_step(lbm_ctx* c) {
+  set_force(*c, c->t);
+  int mode;
+  if (c->spec.pattern == LBM_AB) {
+    mode = MODE_AB;
+  } else {
+    mode = c->phase == 0 ? MODE_AA_EVEN : MODE_AA_ODD;
+  }
+  if (c->spec.collision == LBM_BGK)
+    HIPCHK(c, launch_step_bgk(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), c->stream));
+  else
+    HIPCHK(c, launch_step(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), 0, c->stream));
+  if (c->spec.pattern == LBM_AB) {
+    std::swap(c->popA, c->popB);
+    c->a64.f = c->a32.f = c->popA;
+    c->a64.g = c->a32.g = c->popB;
+  } else {
+    c->phase ^= 1;
+  }
+  c->t += 1;
+  if (c->nee_count > 0) {
+    // velocity / pressure faces at the level just reached
+    set_force(*c, c->t);
+    for (int f = 0; f < 6; ++f) {
+      double pf = c->spec.face_p[f];
+      if (c->spec.FT > 0.0)
+        pf += c->spec.face_pA[f] * std::cos(2.0 * M_PI * (double)c->t / c->spec.FT);
+      c->e64.p[f] = pf;
+      c->e32.p[f] = (float)pf;
+    }
+    const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
+    const void* e = c->spec.storage == LBM_F64 ? (const void*)&c->e64 : (const void*)&c->e32;
+    HIPCHK(c, launch_nee(c->q, c->spec.storage, phase, args_ptr(*c), e, c->nee_nodes,
+                         c->nee_count, c->stream));
+  }
+  return LBM_OK;
+}
+
+// Whether consecutive steps launch identical kernels with identical
+// arguments (apart from the alternation that an even step count undoes).
+bool graph_eligible(const lbm_ctx* c) {
+  if (!c->spec.graphs || c->graph_failed) return false;
+  if (c->spec.FT > 0.0) return false;               // F(t), face p(t) change every step
+  if (c->spec.storage == LBM_F16DEV && c->spec.f16_rounding == LBM_ROUND_STOCHASTIC)
+    return false;                                   // rounding bits depend on t
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st == hipStreamCaptureStatusNone;          // the caller is not capturing
+}
+
+// kGraphSteps steps through the graph for the current parity / buffer order
+// (captured on first use).  The launches are recorded on a private stream
+// of the context (the legacy null stream, torch's default, cannot be
+// captured) and the graph is then launched on the context's stream.
+// Returns LBM_OK, or 1 if no graph could be made (the caller then steps
+// eagerly), or an error status.
+int graph_steps(lbm_ctx* c) {
+  const int key = c->spec.pattern == LBM_AA ? c->phase : (c->popA == c->buf ? 0 : 1);
+  if (!c->gexec[key]) {
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      c->cap_stream = nullptr;
+      c->graph_failed = true;
+      return 1;
+    }
+    const long long t0 = c->t;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      c->graph_failed = true;
+      return 1;
+    }
+    hipStream_t run = c->stream;
+    c->stream = c->cap_stream;
+    int rc = LBM_OK;
+    for (int k = 0; k < kGraphSteps && rc == LBM_OK; ++k) rc = eager_step(c);
+    c->stream = run;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->t = t0;  // nothing has run yet; parity and buffer order are back (even count)
+    if (rc != LBM_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      c->graph_failed = true;
+      return rc != LBM_OK ? rc : 1;
+    }
+    const hipError_t ie = hipGraphInstantiate(&c->gexec[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      c->gexec[key] = nullptr;
+      (void)hipGetLastError();
+      c->graph_failed = true;
+      return 1;
+    }
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec[key], c->stream));
+  c->t += kGraphSteps;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int lbm_step(lbm_ctx* c, long long n) {
   if (!c) return LBM_EINVAL;
   if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
-  const int K = c->spec.monitor_every;
-  for (long long i = 0; i < n; ++i) {
-    set_force(*c, c->t);
-    int mode;
-    if (c->spec.pattern == LBM_AB) {
-      mode = MODE_AB;
-    } else {
-      mode = c->phase == 0 ? MODE_AA_EVEN : MODE_AA_ODD;
+  const long long K = c->spec.monitor_every;
+  long long i = 0;
+  const bool graphs = n >= kGraphSteps && graph_eligible(c);
+  while (i < n) {
+    int rc = 1;
+    if (graphs) {
+      // steps left before the next monitor point (a graph never spans one)
+      const long long span = K > 0 ? std::min(n - i, K - c->t % K) : n - i;
+      if (span >= kGraphSteps) rc = graph_steps(c);
+      if (rc == LBM_OK) i += kGraphSteps;
+      if (rc < 0) return rc;
     }
-    if (c->spec.collision == LBM_BGK)
-      HIPCHK(c, launch_step_bgk(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), c->stream));
-    else
-      HIPCHK(c, launch_step(c->q, c->spec.storage, mode, c->forced, args_ptr(*c), 0, c->stream));
-    if (c->spec.pattern == LBM_AB) {
-      std::swap(c->popA, c->popB);
-      c->a64.f = c->a32.f = c->popA;
-      c->a64.g = c->a32.g = c->popB;
-    } else {
-      c->phase ^= 1;
-    }
-    c->t += 1;
-    if (c->nee_count > 0) {
-      // velocity / pressure faces at the level just reached
-      set_force(*c, c->t);
-      for (int f = 0; f < 6; ++f) {
-        double pf = c->spec.face_p[f];
-        if (c->spec.FT > 0.0)
-          pf += c->spec.face_pA[f] * std::cos(2.0 * M_PI * (double)c->t / c->spec.FT);
-        c->e64.p[f] = pf;
-        c->e32.p[f] = (float)pf;
-      }
-      const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
-      const void* e = c->spec.storage == LBM_F64 ? (const void*)&c->e64 : (const void*)&c->e32;
-      HIPCHK(c, launch_nee(c->q, c->spec.storage, phase, args_ptr(*c), e, c->nee_nodes,
-                           c->nee_count, c->stream));
+    if (rc != LBM_OK) {
+      rc = eager_step(c);
+      if (rc) return rc;
+      i += 1;
     }
     if (K > 0 && c->t % K == 0) {
-      const int rc = run_monitor(c);
+      rc = run_monitor(c);
       if (rc) return rc;
     }
   }
@@ -661,6 +763,7 @@ int lbm_info(const lbm_ctx* c, lbm_info_t* info) {
   info->population_bytes = population_bytes(c->q, c->N, c->spec.storage);
   info->footprint_bytes = c->footprint;
   info->bytes_per_value = bytes_of(c->spec.storage);
+  info->graphs = (c->gexec[0] != nullptr) + (c->gexec[1] != nullptr);
   return LBM_OK;
 }
 
@@ -695,6 +798,9 @@ int lbm_destroy(lbm_ctx* c) {
   if ((c->own_buf && c->buf) || c->mon_buf) (void)hipStreamSynchronize(c->stream);
   if (c->own_buf && c->buf) (void)hipFree(c->buf);
   if (c->mon_buf) (void)hipFree(c->mon_buf);
+  for (auto& g : c->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return LBM_OK;
 }

@@ -56,6 +56,7 @@ class Spec(C.Structure):
         ("dev_buf_bytes", C.c_size_t),
         ("face_p", C.c_double * 6),
         ("face_pA", C.c_double * 6),
+        ("graphs", C.c_int),
     ]
 
 
@@ -68,6 +69,7 @@ class Info(C.Structure):
         ("population_bytes", C.c_size_t),
         ("footprint_bytes", C.c_size_t),
         ("bytes_per_value", C.c_int),
+        ("graphs", C.c_int),
     ]
 
 
@@ -138,7 +140,7 @@ def _dptr(a):
 def make_spec(faces=("wall",) * 6, wall_u=None, F0=(0, 0, 0), FA=(0, 0, 0), FT=0.0, p0=0.0,
               u0=(0, 0, 0), storage="f32", pattern="aa", f16_scale_log2=12,
               f16_rounding="stochastic", collision="mrt", monitor_every=0, stream=None,
-              face_p=None, face_pA=None):
+              face_p=None, face_pA=None, graphs=True):
     """face_p / face_pA: {face name: value} pressures of pressure faces,
     p(t) = face_p + face_pA cos(2 pi t / FT)."""
     sp = Spec()
@@ -168,6 +170,7 @@ def make_spec(faces=("wall",) * 6, wall_u=None, F0=(0, 0, 0), FA=(0, 0, 0), FT=0
     sp.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     sp.monitor_every = int(monitor_every)
     sp.stream = stream
+    sp.graphs = 1 if graphs else 0
     for name, v in (face_p or {}).items():
         sp.face_p[FACES.index(name)] = float(v)
     for name, v in (face_pA or {}).items():
