@@ -188,8 +188,9 @@ int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz,
  *
  * With spec.graphs = 1 the launches of 32 consecutive steps are captured
  * once into a HIP graph and replayed, which removes the per-launch host cost
- * that dominates small lattices.  This happens when the kernel arguments do
- * not change from step to step: a stream the caller is not capturing, no
+ * that dominates small lattices.  This happens for lattices below 2^21 nodes
+ * whose kernel arguments do not change from step to step: a stream the
+ * caller is not capturing, no
  * time-dependent force or face pressure (FT <= 0), and not LBM_F16DEV with
  * stochastic rounding (its rounding bits depend on t).  The graph is
  * recorded on a private stream of the context (the null stream cannot be
