@@ -191,8 +191,8 @@ def main():
     ap.add_argument("--size", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X "
-              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one MI355X; runs over several GPUs are not supported "
+              "(--gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

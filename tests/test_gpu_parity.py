@@ -1,7 +1,7 @@
 """GPU (HIP, through the C ABI) against the FP64 oracle on the same seeded
 inputs.
 
-Tolerances (derived in the design doc):
+Tolerances:
   FP64 storage: populations element-wise within 1e-13 of max|f|;
                 p and u relative L2 (GRE form, Eq. (ed)) <= 1e-12.
   FP32 storage: p and u relative L2 <= 1e-5 (FP32 unit roundoff 6e-8 per
