@@ -4,6 +4,11 @@ Rates follow Sec. 4 of arXiv 1503.03337: s_c = 1.0, s_e = 1.19, s_q = 1.2,
 s_t = 0.98, s_nu = 1/tau with nu = (1/s_nu - 1/2)/3 (Eq. (vis)).  The
 18-velocity model (Appendix B) also needs s_pi, which the paper does not
 give; 1.4 is used.
+
+Under half-way bounce-back the wall of a lattice flow sits exactly half-way
+between nodes only when the odd moments relax at rates tied to s_nu by
+(1/s_nu - 1/2)(1/s_odd - 1/2) = 3/16 (Ginzburg's "magic" combination); with
+fixed odd rates the wall moves with nu.  `odd_rates` returns that s_odd.
 """
 import numpy as np
 
@@ -16,6 +21,14 @@ DUCT_UMAX_COEFF = 0.2946854131260552
 
 def s_nu(nu):
     return 1.0 / (3.0 * nu + 0.5)
+
+
+MAGIC_LAMBDA = 3.0 / 16.0
+
+
+def odd_rates(sn, lam=MAGIC_LAMBDA):
+    """s_odd with (1/sn - 1/2)(1/s_odd - 1/2) = lam."""
+    return 1.0 / (lam / (1.0 / sn - 0.5) + 0.5)
 
 
 def s_vec(q, nu=None, sn=None, s_e=S_E, s_q=S_Q, s_t=S_T, s_pi=S_PI, s_c=S_C):
@@ -35,12 +48,21 @@ DUCT_FACES = ("periodic", "periodic", "wall", "wall", "wall", "wall")
 CAVITY_FACES = ("wall",) * 6
 
 
-def duct(q, edge, length, nu, umax=0.05):
+def duct(q, edge, length, nu, umax=0.05, odd="paper"):
     """Square duct: x periodic (length), y and z half-way walls (edge), body
-    force along x sized for centre-line speed umax."""
+    force along x sized for centre-line speed umax.  odd="magic" ties s_q and
+    s_t to s_nu (odd_rates), so the bounce-back wall error does not grow
+    with nu."""
     a = edge / 2.0
     g = umax * nu / (DUCT_UMAX_COEFF * a * a)
-    return {"model": q, "nx": length, "ny": edge, "nz": edge, "s_vec": s_vec(q, nu),
+    if odd == "magic":
+        so = odd_rates(s_nu(nu))
+        sv = s_vec(q, nu, s_q=so, s_t=so)
+    elif odd == "paper":
+        sv = s_vec(q, nu)
+    else:
+        raise ValueError("odd must be 'paper' or 'magic'")
+    return {"model": q, "nx": length, "ny": edge, "nz": edge, "s_vec": sv,
             "faces": DUCT_FACES, "F0": (g, 0.0, 0.0)}
 
 

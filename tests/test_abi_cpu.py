@@ -103,6 +103,24 @@ def test_params_match_paper_rates():
     assert abs(params.DUCT_UMAX_COEFF - analytic.duct_steady_umax_coeff()) < 1e-14
 
 
+def test_serving_ducts_tie_odd_rates_to_viscosity():
+    """Duct requests relax q and t at s_o with (1/s_nu - 1/2)(1/s_o - 1/2)
+    = 3/16, keeping the paper's even rates; cavities keep the paper's set."""
+    from paper_1503_03337_amd import params, serve
+    for q in (14, 18):
+        for edge in (32, 100, 160):
+            s, _ = serve.request_setup({"q": q, "edge": edge, "kind": "duct"})
+            sn = params.s_nu(serve.duct_nu(edge))
+            odd = [3, 5, 7] + ([13] if q == 14 else [15, 16, 17])
+            for k in odd:
+                assert abs((1 / sn - 0.5) * (1 / s[k] - 0.5) - 3 / 16) < 1e-14
+            assert s[1] == params.S_E and abs(s[8] - sn) < 1e-15
+            if q == 18:
+                assert s[9] == params.S_PI
+        s, _ = serve.request_setup({"q": q, "edge": 64, "kind": "cavity"})
+        assert s[3] == params.S_Q
+
+
 def test_bgk_needs_equal_rates_without_device():
     import numpy as np
     from paper_1503_03337_amd import lbm

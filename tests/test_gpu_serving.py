@@ -60,6 +60,9 @@ def test_plain_and_batched_agree():
 
 
 def test_fp16_duct_accuracy():
+    """Converged edge-32 ducts of both models served batched in FP16
+    deviations: within 1e-3 of the steady series in GRE_u (the error norm of
+    Sec. 4.1) and within 1e-3 u_max of the plain FP32 results pointwise."""
     reqs = [{"id": i, "arrival": 0.0, "kind": "duct", "edge": 32, "q": q, "steps": 12000,
              "stop_residual": None} for i, q in enumerate((14, 18))]
     b16, _ = serve.serve_batched(reqs, "f16dev", keep_fields=True)
@@ -68,14 +71,17 @@ def test_fp16_duct_accuracy():
     def series(Y, Z, a, g, nu):
         return analytic.duct_steady(Y, Z, a, a, g, nu)
 
-    e16 = serve.duct_error(b16, series)
-    e32 = serve.duct_error(p32, series)
-    d = max(np.max(np.abs(a["u"] - b["u"])) for a, b in
-            zip(sorted(b16, key=lambda r: r["id"]), sorted(p32, key=lambda r: r["id"])))
-    print("duct edge 32: max err/u_max FP16 %.2e FP32 %.2e, |FP16-FP32|/u_max %.2e"
-          % (e16, e32, d / serve.DUCT_UMAX))
-    assert d <= 1e-3 * serve.DUCT_UMAX
-    assert e32 < 1e-2 and e16 < 1e-2  # second-order bounce-back error at edge 32
+    b16 = {r["id"]: r for r in b16}
+    p32 = {r["id"]: r for r in p32}
+    for r in reqs:
+        h, f = b16[r["id"]], p32[r["id"]]
+        (hm, hg), (fm, fg) = serve.duct_errors(h, series), serve.duct_errors(f, series)
+        d = np.max(np.abs(h["u"] - f["u"])) / serve.DUCT_UMAX
+        print("q%d duct edge 32: FP16 max %.2e GRE %.2e, FP32 max %.2e GRE %.2e, "
+              "|FP16-FP32|/u_max %.2e" % (r["q"], hm, hg, fm, fg, d))
+        assert hg <= 1e-3 and fg <= 1e-3
+        assert d <= 1e-3
+        assert hm < 2e-3 and fm < 2e-3  # pointwise: second-order wall error at edge 32
 
 
 def test_autotune_picks_valid_tiles():

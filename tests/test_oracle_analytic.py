@@ -128,6 +128,37 @@ def test_force_driven_channel_exact_in_linear_limit(q):
         assert 50 < errs[0] / errs[1] < 200  # quadratic in amplitude
 
 
+def _trt_rates(q, nu, lam=3.0 / 16.0):
+    """All even non-conserved rates at s_nu, all odd ones at s_o with
+    (1/s_nu - 1/2)(1/s_o - 1/2) = lam: the MRT step reduces to two rates."""
+    sn = s_nu_of(nu)
+    so = 1.0 / (lam / (1.0 / sn - 0.5) + 0.5)
+    return svec(q, sn, s_q=so, s_t=so, s_e=sn, s_pi=sn)
+
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_forced_duct_depends_on_lambda_only(q):
+    """Steady forced flow through a square duct with half-way walls: with two
+    rates tied by a fixed lam, the steady solution of the linear problem
+    (u -> 0) is a function of F/nu alone, whatever nu.  Unlike the plane
+    channel the profile is not a polynomial, so this holds only through
+    the exact cancellation of the relaxation rates against the (1 - s/2)
+    source factor and the F/2 velocity shift in every moment, the
+    xyz-type odd moments included."""
+    n, g_over_nu = 8, 1e-7
+    prof = []
+    for nu, steps in ((1.0 / 6.0, 4000), (0.5, 2000), (1.0, 1500)):
+        pr = R.problem(q, 1, n, n, _trt_rates(q, nu), faces=DUCT, F0=(g_over_nu * nu, 0, 0))
+        f = R.run(pr, R.init_eq(pr), 0, steps)
+        prof.append(R.macros(pr, f, steps)[1][0])
+    ref = np.max(np.abs(prof[0]))
+    for u in prof[1:]:
+        # O(u) relative difference from the quadratic terms: 1e-14 here
+        assert np.max(np.abs(u - prof[0])) / ref < 1e-12
+    # and the fixed point is a non-trivial duct profile (not all zero)
+    assert ref > 0.2 * g_over_nu * (n / 2.0) ** 2
+
+
 def _duct_gre(q, n, nu, steps, nx=1, umax=0.05):
     a = n / 2.0
     g = umax * nu / (A.duct_steady_umax_coeff() * a * a)
