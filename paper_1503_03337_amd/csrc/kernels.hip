@@ -68,6 +68,8 @@ __device__ __forceinline__ void pop_store(S* p, S v) {
 
 // ---- storage codecs --------------------------------------------------------
 template <int ST> struct Codec;
+// dec(v, base, 2^-s) and enc(v, base 2^s, 2^s); FP64 and FP32 store the
+// value itself.
 template <> struct Codec<ST_F64> {
   using S = double;
   using C = double;
@@ -80,7 +82,10 @@ template <> struct Codec<ST_F32> {
   static __device__ __forceinline__ C dec(S v, C, C) { return v; }
   static __device__ __forceinline__ S enc(C v, C, C) { return v; }
 };
-// FP16 deviation: stored h = fp16((f - base) 2^s); 2^s and 2^-s are exact.
+// FP16 deviation: stored h = fp16((f - base) 2^s).  Both directions are one
+// fused multiply-add: h 2^-s and f 2^s are exact products (2^s is a power of
+// two), so fma(h, 2^-s, base) rounds exactly like base + h 2^-s, and
+// fma(f, 2^s, -base 2^s) exactly like (f - base) 2^s.
 // enc rounds to nearest.  enc_sr rounds stochastically with gfx950's
 // v_cvt_sr_f16_f32: the top 13 bits of the random word r are added below
 // the 10 mantissa bits FP16 keeps, then the rest is truncated, so a value
@@ -94,17 +99,23 @@ template <> struct Codec<ST_F16> {
   using S = _Float16;
   using C = float;
   static __device__ __forceinline__ C dec(S v, C base, C inv_scale) {
-    return base + static_cast<float>(v) * inv_scale;
+    return __builtin_fmaf(static_cast<float>(v), inv_scale, base);
   }
-  static __device__ __forceinline__ S enc(C v, C base, C scale) {
-    return static_cast<_Float16>((v - base) * scale);
+  static __device__ __forceinline__ S enc(C v, C base_s, C scale) {
+    return static_cast<_Float16>(__builtin_fmaf(v, scale, -base_s));
   }
-  static __device__ __forceinline__ S enc_sr(C v, C base, C scale, unsigned r) {
-    const half2_t zero = {(_Float16)0.0f, (_Float16)0.0f};
-    const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(zero, (v - base) * scale, r, false);
+  static __device__ __forceinline__ S enc_sr(C v, C base_s, C scale, unsigned r) {
+    // the instruction keeps the upper half of its first operand; only the
+    // lower half is stored, so r's own register serves (no extra move)
+    const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, r),
+                                                      __builtin_fmaf(v, scale, -base_s), r, false);
     return h[0];
   }
 };
+
+// Weight class of population a in both models: 0 for the six axis
+// velocities, 1 for the others (the FP16 base depends on nothing else).
+__host__ __device__ constexpr int wclass(int a) { return a < 6 ? 0 : 1; }
 
 // Counter-based random words for the FP16 dither: one hash of (node, time
 // level) per node, then a Weyl sequence over the populations (marginally
@@ -123,16 +134,23 @@ __device__ __forceinline__ unsigned pop_bits(unsigned h, int a) {
   return h + 0x9E3779B9u * (unsigned)(a + 1);
 }
 
-// Encode a post-collision value: FP16 with the step's rounding mode, the
-// other storages plainly.
-template <int ST>
+// Encode a post-collision value: FP16 stochastically (SR) or to nearest,
+// the other storages plainly.  SR is a template argument so that a kernel
+// picks the rounding mode once per node, not once per population.
+template <int ST, bool SR>
 __device__ __forceinline__ typename Codec<ST>::S enc_step(const LatticeArgs<typename Codec<ST>::C>& A,
                                                           typename Codec<ST>::C v, int slot,
                                                           unsigned h, int a) {
-  if constexpr (ST == ST_F16) {
-    if (A.f16_sr) return Codec<ST>::enc_sr(v, A.base[slot], A.scale, pop_bits(h, a));
-  }
-  return Codec<ST>::enc(v, A.base[slot], A.scale);
+  const typename Codec<ST>::C bs = A.base_s[wclass(slot)];
+  if constexpr (ST == ST_F16 && SR) return Codec<ST>::enc_sr(v, bs, A.scale, pop_bits(h, a));
+  return Codec<ST>::enc(v, bs, A.scale);
+}
+// The same with the mode read per value (code off the per-node hot path).
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::S enc_any(const LatticeArgs<typename Codec<ST>::C>& A,
+                                                         typename Codec<ST>::C v, int slot,
+                                                         unsigned h, int a) {
+  return A.f16_sr ? enc_step<ST, true>(A, v, slot, h, a) : enc_step<ST, false>(A, v, slot, h, a);
 }
 
 // ---- neighbour offsets -----------------------------------------------------
@@ -222,6 +240,40 @@ __device__ __forceinline__ void link(const Nbr& b, const LatticeArgs<C>& A, int 
   slot = fz ? hi : lo;
 }
 
+// ---- population addresses ---------------------------------------------------
+// Byte address of a stored value: the node's own address p0 = buf + n b
+// (one per lane and node), plus the neighbour offset times b, plus the
+// population array's offset pofs[slot] (a kernel argument: uniform, no
+// multiply in the kernel).  On the inner path (GEN = false: y and z interior,
+// no symmetry planes) only the x part of the neighbour offset varies across
+// lanes, so each node forms p0 and its two x-shifted copies once and every
+// population's address is one 64-bit add of a uniform offset.  The general
+// path also handles mirror slots across symmetry planes (slot chosen per
+// lane), with slot * pbytes.
+template <typename S>
+__device__ __forceinline__ const char* lane_ptr(const void* buf, unsigned n) {
+  return static_cast<const char*>(buf) + (unsigned long long)n * sizeof(S);
+}
+
+// Address of slot `slot` at node n + off on either path (link() semantics:
+// off, slot for population a moving along (cx, cy, cz)); px[k] = p0 + the
+// x offset of direction k (inner path only).
+template <typename S, bool GEN, typename C>
+__device__ __forceinline__ const char* link_ptr(const LatticeArgs<C>& A, const Nbr& b,
+                                                const char* p0, const char* const (&px)[2],
+                                                int cx, int cy, int cz, int off, int slot,
+                                                int slot_inner) {
+  if constexpr (GEN) {
+    return p0 + (long long)off * (long long)sizeof(S) + (long long)slot * A.pbytes;
+  } else {
+    // slot == slot_inner here (no symmetry planes on the inner path)
+    long long u = A.pofs[slot_inner];
+    if (cy) u += (long long)b.oy[cy > 0] * (long long)sizeof(S);
+    if (cz) u += (long long)b.oz[cz > 0] * (long long)sizeof(S);
+    return (cx ? px[cx > 0] : p0) + u;
+  }
+}
+
 // ---- reading the populations of node n ------------------------------------
 // PHASE 0: natural layout (AB, AA even).  PHASE 1: AA swapped layout after
 // an even step: f_a(x) = A[abar][x - c_a], or, when x - c_a is a wall,
@@ -235,14 +287,18 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
                                           int y, int z, typename Codec<ST>::C (&f)[Q]) {
   using CD = Codec<ST>;
   using C = typename CD::C;
+  using S = typename CD::S;
   using L = Lattice<Q>;
-  const long long st = A.stride;
+  const char* p0 = lane_ptr<S>(src, n);
   if (PHASE == 0) {
 #pragma unroll
     for (int a = 0; a < Q; ++a)
-      f[a] = CD::dec(pop_load<NT>(src + a * st + n), A.base[a], A.inv_scale);
+      f[a] = CD::dec(pop_load<NT>((const S*)(p0 + A.pofs[a])), A.base[wclass(a)], A.inv_scale);
   } else {
     const Nbr b = make_nbr<GEN>(A, x, y, z);
+    // x - c_a: direction k = (-cx > 0) of the link taken from this node
+    const char* const px[2] = {p0 + (long long)b.ox[0] * (long long)sizeof(S),
+                               p0 + (long long)b.ox[1] * (long long)sizeof(S)};
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int o = L::opp[a];
@@ -250,8 +306,10 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
       bool wall;
       C term;
       link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term, slot);
-      const long long idx = wall ? (a * st + n) : (slot * st + (long long)(n + off));
-      f[a] = CD::dec(pop_load<NT>(src + idx), A.base[a], A.inv_scale);
+      const char* nb = link_ptr<S, GEN>(A, b, p0, px, -L::cx[a], -L::cy[a], -L::cz[a], off,
+                                        slot, o);
+      const char* p = wall ? p0 + A.pofs[a] : nb;
+      f[a] = CD::dec(pop_load<NT>((const S*)p), A.base[wclass(a)], A.inv_scale);
     }
   }
 }
@@ -262,19 +320,23 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
 // population, rounded once, as in the push patterns).  Otherwise push to
 // x + c_a (or bounce back into slot abar of this node across a wall, or,
 // across symmetry planes only, into the mirror slot of the node reached by
-// moving along the planes).
-template <int Q, int ST, int MODE, bool GEN>
+// moving along the planes).  The wall term is +0 off walls and f - (+0) is
+// f bit for bit, so every store is f_a - term at a selected address (no
+// branch); a slot and its mirror image or opposite share a's weight, hence
+// its FP16 base.
+template <int Q, int ST, int MODE, bool GEN, bool SR>
 __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>::C>& A,
                                            typename Codec<ST>::S* dst, unsigned n, int x, int y,
                                            int z, const typename Codec<ST>::C (&f)[Q]) {
   using CD = Codec<ST>;
   using C = typename CD::C;
+  using S = typename CD::S;
   using L = Lattice<Q>;
-  const long long st = A.stride;
   // dither bits of the value population a leaves this node with at level t
   const unsigned h = (ST == ST_F16) ? node_hash(n, A.tstep) : 0u;
+  char* p0 = const_cast<char*>(lane_ptr<S>(dst, n));
+  const Nbr b = make_nbr<GEN>(A, x, y, z);
   if (MODE == MODE_AA_EVEN) {
-    const Nbr b = make_nbr<GEN>(A, x, y, z);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int o = L::opp[a];
@@ -282,10 +344,11 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       bool wall;
       C term;
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
-      pop_store(dst + o * st + n, enc_step<ST>(A, wall ? f[a] - term : f[a], o, h, a));
+      pop_store((S*)(p0 + A.pofs[o]), enc_step<ST, SR>(A, f[a] - term, o, h, a));
     }
   } else {
-    const Nbr b = make_nbr<GEN>(A, x, y, z);
+    const char* const px[2] = {p0 + (long long)b.ox[0] * (long long)sizeof(S),
+                               p0 + (long long)b.ox[1] * (long long)sizeof(S)};
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const int o = L::opp[a];
@@ -293,11 +356,9 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       bool wall;
       C term;
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
-      // (a mirror image has a's weight, hence a's FP16 base)
-      if (wall)
-        pop_store(dst + o * st + n, enc_step<ST>(A, f[a] - term, o, h, a));
-      else
-        pop_store(dst + slot * st + (long long)(n + off), enc_step<ST>(A, f[a], a, h, a));
+      const char* nb = link_ptr<S, GEN>(A, b, p0, px, L::cx[a], L::cy[a], L::cz[a], off, slot, a);
+      char* p = const_cast<char*>(wall ? p0 + A.pofs[o] : nb);
+      pop_store((S*)p, enc_step<ST, SR>(A, f[a] - term, o, h, a));
     }
   }
 }
@@ -330,7 +391,11 @@ __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::
     }
     collide<Q, C, FORCED>(f, r, F);
   }
-  write_node<Q, ST, MODE, GEN>(A, static_cast<S*>(MODE == MODE_AB ? A.g : A.f), n, x, y, z, f);
+  S* dst = static_cast<S*>(MODE == MODE_AB ? A.g : A.f);
+  if (ST == ST_F16 && A.f16_sr)
+    write_node<Q, ST, MODE, GEN, true>(A, dst, n, x, y, z, f);
+  else
+    write_node<Q, ST, MODE, GEN, false>(A, dst, n, x, y, z, f);
 }
 
 // Dispatch on whether this node's wavefront may touch a y or z boundary
@@ -457,10 +522,7 @@ __global__ __launch_bounds__(256) void k_set_pop(LatticeArgs<typename Codec<ST>:
   using C = typename CD::C;
   const long long N = (long long)A.nx * A.ny * A.nz;
   typename CD::S* dst = static_cast<typename CD::S*>(A.f) + a * A.stride;
-  C base = A.base[0];
-#pragma unroll
-  for (int k = 1; k < Q; ++k)
-    if (k == a) base = A.base[k];
+  const C base = A.base_s[wclass(a)];
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
        n += (long long)gridDim.x * blockDim.x)
     dst[n] = CD::enc((C)in[n], base, A.scale);
@@ -491,7 +553,7 @@ __global__ __launch_bounds__(256) void k_init_eq(LatticeArgs<typename Codec<ST>:
       const double w = weight<Q>(a);
       const double cu = L::cx[a] * jx + L::cy[a] * jy + L::cz[a] * jz;
       const double fe = 3.0 * w * pn + w * (3.0 * cu + 4.5 * cu * cu - 1.5 * jsq);
-      dst[a * A.stride + n] = CD::enc((C)fe, A.base[a], A.scale);
+      dst[a * A.stride + n] = CD::enc((C)fe, A.base_s[wclass(a)], A.scale);
     }
   }
 }
@@ -601,7 +663,7 @@ __device__ __forceinline__ void store_node(const LatticeArgs<typename Codec<ST>:
   if (PHASE == 0) {
 #pragma unroll
     for (int a = 0; a < Q; ++a)
-      if (sel & (1u << a)) pop_store(dst + a * st + n, enc_step<ST>(A, f[a], a, h, a));
+      if (sel & (1u << a)) pop_store(dst + a * st + n, enc_any<ST>(A, f[a], a, h, a));
   } else {
     const Nbr b = make_nbr<true>(A, x, y, z);
 #pragma unroll
@@ -613,7 +675,7 @@ __device__ __forceinline__ void store_node(const LatticeArgs<typename Codec<ST>:
       C term;
       link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term, slot);
       const long long idx = wall ? (a * st + n) : (slot * st + (long long)(n + off));
-      pop_store(dst + idx, enc_step<ST>(A, f[a], a, h, a));
+      pop_store(dst + idx, enc_any<ST>(A, f[a], a, h, a));
     }
   }
 }

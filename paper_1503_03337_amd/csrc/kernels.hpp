@@ -36,6 +36,8 @@ template <typename C> struct LatticeArgs {
   void* f;                 // populations (AB: the copy read this step)
   void* g;                 // AB: the copy written this step; AA: == f
   long long stride;        // elements between population arrays (= N)
+  long long pbytes;        // stride in bytes of the stored type
+  long long pofs[18];      // a * pbytes: byte offset of population array a
   int nx, ny, nz;
   int per_x, per_y, per_z; // periodic axes
   int sym;                 // bit f set: face f (-x,+x,-y,+y,-z,+z) is a
@@ -45,7 +47,9 @@ template <typename C> struct LatticeArgs {
   C bb[18][3];             // 6 w_a (c_a . u_w) for link a leaving through
                            // the x / y / z face it crosses
   C F[3];                  // body force at this step
-  C base[18];              // FP16 deviation base 3 w_a p0
+  C base[2], base_s[2];    // FP16 deviation base 3 w_a p0 of the axis (a < 6)
+                           // and the other populations, and base 2^s (exact:
+                           // 2^s is a power of two); w_a takes two values
   C scale, inv_scale;      // FP16 2^s, 2^-s
   unsigned tstep;          // time level t of this step (FP16 rounding dither)
   int f16_sr;              // FP16 stores: 1 stochastic rounding, 0 nearest

@@ -63,6 +63,13 @@ __host__ __device__ constexpr int mirror(int a, int mask) {
   return -1;
 }
 
+// k x + y in one instruction, for k a power of two (+-0.5, +-2, +-4): k x
+// is then exact, so the fused result has the bits of the separate multiply
+// and add.  Only such products are fused; every other product keeps its own
+// rounding.
+__device__ __forceinline__ float fma2(float k, float x, float y) { return __builtin_fmaf(k, x, y); }
+__device__ __forceinline__ double fma2(double k, double x, double y) { return __builtin_fma(k, x, y); }
+
 // Per-moment relaxation coefficients, pre-divided by the row norms:
 //   sN_k = s_k / N_k,   hN_k = (1 - s_k/2) / N_k,
 // so that d_k = D_k / N_k = sN_k (m_k - meq_k) - hN_k mF_k.
@@ -94,19 +101,19 @@ __device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C
   const C Kx = px + mx, Kxz = px - mx, Kxy = pxy + mxy, Kxyz = pxy - mxy;
 
   const C mP = A + K0;
-  const C me = C(3) * K0 - C(4) * A;
-  const C jx = dx + Kx, qx = Kx - C(4) * dx;
-  const C jy = dy + Ky, qy = Ky - C(4) * dy;
-  const C jz = dz + Kz, qz = Kz - C(4) * dz;
-  const C pxx3 = C(2) * ax - ay - az;
+  const C me = fma2(C(-4), A, C(3) * K0);
+  const C jx = dx + Kx, qx = fma2(C(-4), dx, Kx);
+  const C jy = dy + Ky, qy = fma2(C(-4), dy, Ky);
+  const C jz = dz + Kz, qz = fma2(C(-4), dz, Kz);
+  const C pxx3 = fma2(C(2), ax, -ay) - az;
   const C pww = ay - az;
 
   // Eq. (hgl): u = j + F/2, p = 3/7 (P - |u|^2/3)
   C ux = jx, uy = jy, uz = jz;
   if (FORCED) {
-    ux += C(0.5) * F[0];
-    uy += C(0.5) * F[1];
-    uz += C(0.5) * F[2];
+    ux = fma2(C(0.5), F[0], ux);
+    uy = fma2(C(0.5), F[1], uy);
+    uz = fma2(C(0.5), F[2], uz);
   }
   const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
   const C usq = uxx + uyy + uzz;
@@ -139,7 +146,7 @@ __device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C
     d5 -= r.hN[5] * (C(-7.0 / 3.0) * Fy);
     d6 -= r.hN[6] * Fz;
     d7 -= r.hN[7] * (C(-7.0 / 3.0) * Fz);
-    d8 -= r.hN[8] * (C(6) * ux * Fx - C(2) * w);
+    d8 -= r.hN[8] * fma2(C(-2), w, C(6) * ux * Fx);
     d9 -= r.hN[9] * (C(2) * (uy * Fy - uz * Fz));
     d10 -= r.hN[10] * (ux * Fy + uy * Fx);
     d11 -= r.hN[11] * (uy * Fz + uz * Fy);
@@ -147,11 +154,10 @@ __device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C
   }
 
   // back-transform f*_a = f_a - sum_k T_ka d_k, axis velocities
-  const C bA = d0 - C(4) * d1e;
-  const C X = d2 - C(4) * d3, Y = d4 - C(4) * d5, Z = d6 - C(4) * d7;
-  const C t8 = C(2) * d8;
-  f[0] -= (bA + X) + t8;
-  f[1] -= (bA - X) + t8;
+  const C bA = fma2(C(-4), d1e, d0);
+  const C X = fma2(C(-4), d3, d2), Y = fma2(C(-4), d5, d4), Z = fma2(C(-4), d7, d6);
+  f[0] -= fma2(C(2), d8, bA + X);
+  f[1] -= fma2(C(2), d8, bA - X);
   const C yy = d9 - d8, zz = -(d8 + d9);
   f[2] -= (bA + Y) + yy;
   f[3] -= (bA - Y) + yy;
@@ -208,34 +214,34 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
 
   const C E = Sxy + Sxz + Syz;
   const C mP = A + E;
-  const C me = E - C(2) * A;
+  const C me = fma2(C(-2), A, E);
   const C ex = Xxy + Xxz, ey = Yxy + Yyz, ez = Zxz + Zyz;
-  const C jx = dx + ex, qx = ex - C(4) * dx;
-  const C jy = dy + ey, qy = ey - C(4) * dy;
-  const C jz = dz + ez, qz = ez - C(4) * dz;
-  const C axis_xx = C(2) * ax - ay - az;
-  const C edge_xx = (Sxy + Sxz) - C(2) * Syz;
+  const C jx = dx + ex, qx = fma2(C(-4), dx, ex);
+  const C jy = dy + ey, qy = fma2(C(-4), dy, ey);
+  const C jz = dz + ez, qz = fma2(C(-4), dz, ez);
+  const C axis_xx = fma2(C(2), ax, -ay) - az;
+  const C edge_xx = fma2(C(-2), Syz, Sxy + Sxz);
   const C pxx3 = axis_xx + edge_xx;
-  const C pixx3 = edge_xx - C(2) * axis_xx;
+  const C pixx3 = fma2(C(-2), axis_xx, edge_xx);
   const C axis_ww = ay - az, edge_ww = Sxy - Sxz;
   const C pww = axis_ww + edge_ww;
-  const C piww = edge_ww - C(2) * axis_ww;
+  const C piww = fma2(C(-2), axis_ww, edge_ww);
   const C tx = Xxy - Xxz, ty = Yyz - Yxy, tz = Zxz - Zyz;
 
   C ux = jx, uy = jy, uz = jz;
   if (FORCED) {
-    ux += C(0.5) * F[0];
-    uy += C(0.5) * F[1];
-    uz += C(0.5) * F[2];
+    ux = fma2(C(0.5), F[0], ux);
+    uy = fma2(C(0.5), F[1], uy);
+    uz = fma2(C(0.5), F[2], uz);
   }
   const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
   const C usq = uxx + uyy + uzz;
   // Eq. (hgl) with w0 = 1/3: p = (P - |u|^2/2) / 2
-  const C p = (mP - C(0.5) * usq) * C(0.5);
+  const C p = fma2(C(-0.5), usq, mP) * C(0.5);
   const C qxx = C(3) * uxx - usq, qww = uyy - uzz;
 
-  C d0 = r.sN[0] * (mP - (C(2) * p + C(0.5) * usq));
-  C d1e = r.sN[1] * (me - (C(0.5) * usq - p));
+  C d0 = r.sN[0] * (mP - fma2(C(2), p, C(0.5) * usq));
+  C d1e = r.sN[1] * (me - fma2(C(0.5), usq, -p));
   C d2 = r.sN[2] * (jx - ux);
   C d3 = r.sN[3] * (qx + C(2.0 / 3.0) * ux);
   C d4 = r.sN[4] * (jy - uy);
@@ -243,9 +249,9 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
   C d6 = r.sN[6] * (jz - uz);
   C d7 = r.sN[7] * (qz + C(2.0 / 3.0) * uz);
   C d8 = r.sN[8] * (pxx3 - qxx);
-  C d9 = r.sN[9] * (pixx3 + C(0.5) * qxx);
+  C d9 = r.sN[9] * fma2(C(0.5), qxx, pixx3);
   C d10 = r.sN[10] * (pww - qww);
-  C d11 = r.sN[11] * (piww + C(0.5) * qww);
+  C d11 = r.sN[11] * fma2(C(0.5), qww, piww);
   C d12 = r.sN[12] * (XYxy - ux * uy);
   C d13 = r.sN[13] * (YZyz - uy * uz);
   C d14 = r.sN[14] * (XZxz - ux * uz);
@@ -255,7 +261,7 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
   if (FORCED) {
     const C Fx = F[0], Fy = F[1], Fz = F[2];
     const C w = ux * Fx + uy * Fy + uz * Fz;
-    const C gxx = C(6) * ux * Fx - C(2) * w;
+    const C gxx = fma2(C(-2), w, C(6) * ux * Fx);
     const C gww = uy * Fy - uz * Fz;
     d0 -= r.hN[0] * w;
     d1e -= r.hN[1] * w;
@@ -275,11 +281,11 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
   }
 
   // back-transform, axis velocities (columns 1..6 of T)
-  const C bA = d0 - C(2) * d1e;
-  const C X = d2 - C(4) * d3, Y = d4 - C(4) * d5, Z = d6 - C(4) * d7;
-  const C xx = C(2) * d8 - C(4) * d9;
-  const C yz_common = C(2) * d9 - d8;  // -d8 + 2 d9
-  const C ww = d10 - C(2) * d11;
+  const C bA = fma2(C(-2), d1e, d0);
+  const C X = fma2(C(-4), d3, d2), Y = fma2(C(-4), d5, d4), Z = fma2(C(-4), d7, d6);
+  const C xx = fma2(C(2), d8, C(-4) * d9);
+  const C yz_common = fma2(C(2), d9, -d8);  // -d8 + 2 d9
+  const C ww = fma2(C(-2), d11, d10);
   const C yy = yz_common + ww, zz = yz_common - ww;
   f[0] -= (bA + X) + xx;
   f[1] -= (bA - X) + xx;
@@ -311,7 +317,7 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
     f[13] -= a - b;
   }
   {  // yz plane (cy, cz)
-    const C W0 = E0 - C(2) * G, W1 = jqy + d16, W2 = jqz - d17, W12 = d13;
+    const C W0 = fma2(C(-2), G, E0), W1 = jqy + d16, W2 = jqz - d17, W12 = d13;
     C a = W0 + W2, b = W1 + W12;
     f[14] -= a + b;
     f[15] -= a - b;
@@ -344,9 +350,9 @@ __device__ __forceinline__ void collide_bgk(C (&f)[Q], C omega, C hom, const C (
   }
   C ux = jx, uy = jy, uz = jz;
   if (FORCED) {
-    ux += C(0.5) * F[0];
-    uy += C(0.5) * F[1];
-    uz += C(0.5) * F[2];
+    ux = fma2(C(0.5), F[0], ux);
+    uy = fma2(C(0.5), F[1], uy);
+    uz = fma2(C(0.5), F[2], uz);
   }
   const C usq = ux * ux + uy * uy + uz * uz;
   // Eq. (hgl): p = (P - 3/2 w0 |u|^2) / (3 (1 - w0))

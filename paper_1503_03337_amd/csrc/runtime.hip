@@ -217,6 +217,8 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
   A.f = c.popA;
   A.g = c.popB ? c.popB : c.popA;
   A.stride = (long long)pop_stride(c.N);
+  A.pbytes = A.stride * (c.spec.storage == LBM_F64 ? 8 : c.spec.storage == LBM_F32 ? 4 : 2);
+  for (int a = 0; a < 18; ++a) A.pofs[a] = a * A.pbytes;
   A.nx = c.nx;
   A.ny = c.ny;
   A.nz = c.nz;
@@ -250,11 +252,15 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
       const double cu = cx[a] * uw[0] + cy[a] * uw[1] + cz[a] * uw[2];
       A.bb[a][d] = (C)(6.0 * w[a] * cu);
     }
-    A.base[a] = (C)(3.0 * w[a] * c.spec.p0);
   }
   const double sc = std::ldexp(1.0, c.spec.f16_scale_log2);
   A.scale = (C)sc;
   A.inv_scale = (C)(1.0 / sc);
+  // one base per weight class: the axis populations (a < 6) and the rest
+  for (int k = 0; k < 2; ++k) {
+    A.base[k] = (C)(3.0 * w[k == 0 ? 0 : 6] * c.spec.p0);
+    A.base_s[k] = A.base[k] * A.scale;
+  }
   A.F[0] = A.F[1] = A.F[2] = 0;
   A.tstep = (unsigned)c.t;
   A.f16_sr = c.spec.f16_rounding == LBM_ROUND_STOCHASTIC ? 1 : 0;
