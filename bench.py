@@ -70,9 +70,12 @@ def time_steps(torch, lat, steps):
     return wall, e0.elapsed_time(e1) / 1e3
 
 
-def copy_bandwidth(torch, lbm, nbytes=1 << 30, reps=20):
+def copy_bandwidth(torch, lbm, nbytes=1 << 30, reps=20, in_place=False):
+    """Bytes read + written per second by the plain copy kernel over nbytes
+    (in place: source and destination are the same buffer, as in the AA
+    step)."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = src if in_place else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     lbm.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, 2, stream.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -221,6 +224,7 @@ def main():
     bwall, bev = time_steps(torch, big, bsteps)
     big.close()
     copy_gbs = copy_bandwidth(torch, lbm)
+    copy_inplace_gbs = copy_bandwidth(torch, lbm, in_place=True)
     b256 = batch256(torch, lbm, params)
     collisions = mrt_vs_lbgk(torch, lbm, params)
     storages = storage_variants(torch, lbm, params)
@@ -248,6 +252,7 @@ def main():
         "cavity256": {"MLUPS": round(256 ** 3 * bsteps / bwall / 1e6, 1),
                       "achieved_GBs": round(bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9, 1)},
         "copy_probe_GBs": round(copy_gbs, 1),
+        "copy_probe_inplace_GBs": round(copy_inplace_gbs, 1),
         "batch256": b256,
         "collision_cost": collisions,
         "storage_variants": storages,

@@ -1008,19 +1008,22 @@ hipError_t launch_reduce_partials(const double* partial, int nb, double* out, hi
 }
 
 // ---- measurement helper: plain streaming copy ---------------------------------
-// Each thread moves 4 x 16 bytes, all four loads issued before the stores,
-// one workgroup per 16 KB: the achievable-bandwidth reference.
+// Each thread moves 2 x 16 bytes, both loads issued before the stores, one
+// workgroup per 8 KB.  Of the variants measured on MI355X (1-4 GiB, in place
+// and not) this one is the fastest: 4 x 16 B per thread is 3-4 % slower and
+// 8 x 16 B 28 % slower; non-temporal stores do not help.  It is the
+// achievable-bandwidth reference the step kernels are read against.
 __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
                                               uint4* __restrict__ dst, long long n16) {
-  const long long base = blockIdx.x * 1024LL + threadIdx.x;
-  uint4 v[4];
+  const long long base = blockIdx.x * 512LL + threadIdx.x;
+  uint4 v[2];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 2; ++k) {
     const long long i = base + 256LL * k;
     if (i < n16) v[k] = src[i];
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 2; ++k) {
     const long long i = base + 256LL * k;
     if (i < n16) dst[i] = v[k];
   }
@@ -1029,7 +1032,7 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src,
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t s) {
   clear_stale_error();
   const long long n16 = (long long)(bytes / 16);
-  long long nb = (n16 + 1023) / 1024;
+  long long nb = (n16 + 511) / 512;
   if (nb < 1) nb = 1;
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, (const uint4*)src, (uint4*)dst,
