@@ -164,3 +164,38 @@ def test_plain_c_program_links_and_validates():
     out = subprocess.run([exe, "--check-only"], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0, out.stderr
     assert "validation ok" in out.stdout
+
+
+def test_duct_error_norms_on_constructed_fields():
+    """serve.duct_errors on fields with known errors: the exact series gives
+    0, a uniform relative error e in u_x gives GRE_u = e and a max error of
+    e * max|u| / u_max, a cross-flow v adds to GRE_u only."""
+    import numpy as np
+    from oracle import analytic
+    from paper_1503_03337_amd import params, serve
+    L = 12
+    a = L / 2.0
+    nu = serve.duct_nu(L)
+    g = serve.DUCT_UMAX * nu / (params.DUCT_UMAX_COEFF * a * a)
+    y = np.arange(L) + 0.5 - a
+    Y, Z = np.meshgrid(y, y, indexing="xy")
+
+    def series(Yv, Zv, av, gv, nuv):
+        return analytic.duct_steady(Yv, Zv, av, av, gv, nuv)
+
+    ua = series(Y, Z, a, g, nu)
+    u = np.zeros((3, L, L, L))
+    u[0] = ua[:, :, None]
+    rec = {"edge": L, "u": u}
+    assert serve.duct_errors(rec, series) == (0.0, 0.0)
+    eps = 1e-3
+    u[0] *= 1.0 + eps
+    emax, gre = serve.duct_errors(rec, series)
+    assert abs(gre - eps) < 1e-12
+    assert abs(emax - eps * np.max(ua) / serve.DUCT_UMAX) < 1e-12
+    u[0] = ua[:, :, None]
+    u[1] = 0.5e-3 * np.max(ua)
+    emax, gre = serve.duct_errors(rec, series)
+    assert emax == 0.0
+    expect = 0.5e-3 * np.max(ua) * np.sqrt(L ** 3 / (L * np.sum(ua ** 2)))
+    assert abs(gre - expect) < 1e-12 * max(1.0, expect)
