@@ -98,7 +98,7 @@ def batch256(torch, lbm, params, steps=100):
         cfg = params.cavity(q, edge, 400.0)
         return lbm.Lattice(q, edge, edge, edge, cfg["s_vec"], faces=cfg["faces"],
                            wall_u=cfg["wall_u"], storage="f32", pattern="aa")
-    tiles, _ = autotune.tune(mk, {(c["q"], c["edge"]) for c in spec}, steps=20, reps=1)
+    tiles, _ = autotune.tune(mk, {(c["q"], c["edge"]) for c in spec})
     lats, b = [], lbm.Batch(torch.cuda.current_stream().cuda_stream)
     for c in spec:
         L = c["edge"]

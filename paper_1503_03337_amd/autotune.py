@@ -7,6 +7,10 @@ and aligned whatever the edge) or a tx x ty tile of one x-y plane (tx * ty
 every (q, edge bucket) present in a batch the tuner times each candidate on
 a batch of copies of that bucket's median member, large enough (>= 2^22
 nodes) to run from HBM as the real batch does, and keeps the fastest.  The
+timing lattices first run `warm` steps (the lid drives them away from the
+all-zero start, which streams faster than developed flow), each candidate is
+timed `reps` times and its best kept, and a tile must beat the flat mapping
+by `margin` to replace it (differences below that are timing noise).  The
 mapping never changes results (each node's arithmetic is the same), only
 speed.
 """
@@ -35,7 +39,8 @@ def bucket(edge, width=8):
     return (edge // width) * width
 
 
-def tune(make_lattice, keys, steps=40, reps=2, stream=None, sync=None, min_nodes=1 << 22):
+def tune(make_lattice, keys, steps=40, reps=3, stream=None, sync=None, min_nodes=1 << 22,
+         warm=200, margin=0.02):
     """keys: iterable of (q, edge).  make_lattice(q, edge) returns a fresh
     lbm.Lattice (FP32 or FP16DEV, AA).  Returns {(q, bucket(edge)): (tx, ty)}
     ((0, 0): the flat mapping) and the measured MLUPS per candidate."""
@@ -49,6 +54,12 @@ def tune(make_lattice, keys, steps=40, reps=2, stream=None, sync=None, min_nodes
         copies = max(2, -(-min_nodes // sample ** 3))
         lats = [make_lattice(q, sample) for _ in range(copies)]
         nodes = sum(l.N for l in lats)
+        if warm > 0:
+            b = lbm.Batch(lats[0].stream)
+            for l in lats:
+                b.add(l, 10 ** 9)
+            b.step(warm)
+            b.close()
         results = {}
         for tile in candidates(sample):
             b = lbm.Batch(lats[0].stream)
@@ -67,7 +78,10 @@ def tune(make_lattice, keys, steps=40, reps=2, stream=None, sync=None, min_nodes
             results[tile] = nodes * steps / t / 1e6
         for l in lats:
             l.close()
-        best[(q, bk)] = max(results, key=results.get)
+        pick = max(results, key=results.get)
+        if results[pick] < (1.0 + margin) * results[(0, 0)]:
+            pick = (0, 0)
+        best[(q, bk)] = pick
         log[(q, bk)] = results
     return best, log
 

@@ -303,7 +303,7 @@ def bench_summary(n=24, seed=1, budget_gib=16):
 
     def mk(q, edge):
         return make_lattice({"q": q, "edge": edge, "kind": "cavity"}, "f32")
-    tiles, _ = at.tune(mk, keys, steps=20, reps=1)
+    tiles, _ = at.tune(mk, keys)
     budget = budget_gib << 30
     res = {"trace": {"requests": n, "rate_per_s": round(rate, 3), "seed": seed,
                      "budget_GiB": budget_gib}}
