@@ -102,7 +102,8 @@ typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
  * mirroring.
  *
  * Velocity, pressure and node-layer symmetry faces need at least 3 nodes on
- * their axis, and run on single lattices only (batches reject them).
+ * their axis; in a batch their pass runs once per class and step over the
+ * boundary nodes of all members that have such faces.
  *
  * wall_u is used on wall and velocity faces and ignored elsewhere. */
 typedef enum {
@@ -263,9 +264,10 @@ int lbm_destroy(lbm_ctx* ctx);
 
 /* ---- batched execution ------------------------------------------------
  * A batch advances many independent contexts (any mix of q = 14 / 18,
- * storage FP32 / FP16DEV, pattern AA, MRT collision, shapes, periodic /
- * wall / symmetry faces, forces and rates) with one kernel launch per time
- * step and (q, storage) class covering all of them; each
+ * storage FP32 / FP16DEV, pattern AA, MRT collision, shapes, face kinds,
+ * forces and rates) with one kernel launch per time step and (q, storage)
+ * class covering all of them (plus one launch for the velocity / pressure /
+ * node-layer symmetry pass when any member of the class has such faces); each
  * member keeps its own time level, parity and populations, and its result
  * is bit-identical to running it alone in a batch.  Members must share the
  * batch's stream.  Members can be added and removed between calls

@@ -712,7 +712,8 @@ __device__ __forceinline__ unsigned mirror_arrivals(const NeeArgs<C>& E, const i
   return sel;
 }
 
-// One thread per listed boundary node x_b.  On velocity / pressure faces
+// The pass at one listed boundary node x_b (k_nee: one thread per node of
+// a lattice's list; k_batch_nee: of a batch class's lists).  On velocity / pressure faces
 // (non-equilibrium extrapolation): inward neighbour x_f (never on such a
 // face itself, as each such axis has >= 3 nodes; if it lies on a node-layer
 // symmetry plane its arriving populations are taken mirrored, as that
@@ -726,15 +727,13 @@ __device__ __forceinline__ unsigned mirror_arrivals(const NeeArgs<C>& E, const i
 // read but not used, the mirrored values standing in for them exactly as
 // the owner computes them, so the result does not depend on thread order.
 template <int Q, int ST, int PHASE>
-__global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> A,
-                                             NeeArgs<typename Codec<ST>::C> E,
-                                             const int* __restrict__ nodes, int count) {
+__device__ __forceinline__ void nee_node(const LatticeArgs<typename Codec<ST>::C>& A,
+                                         const NeeArgs<typename Codec<ST>::C>& E, unsigned n) {
   using CD = Codec<ST>;
   using C = typename CD::C;
   using L = Lattice<Q>;
   const int dim[3] = {A.nx, A.ny, A.nz};
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-    const unsigned n = (unsigned)nodes[i];
+  {
     int x, y, z;
     node_xyz(n, A.nx, A.ny, x, y, z);
     const int own[3] = {x, y, z};
@@ -763,7 +762,7 @@ __global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> 
       read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), n, x, y, z, f);
       const unsigned sel = mirror_arrivals<Q, C>(E, dim, own, f);
       store_node<Q, ST, PHASE>(A, static_cast<typename CD::S*>(A.f), n, x, y, z, f, h, sel);
-      continue;
+      return;
     }
     const unsigned m = (unsigned)src[0] + (unsigned)A.nx * ((unsigned)src[1] + (unsigned)A.ny * (unsigned)src[2]);
     C ff[Q];
@@ -796,6 +795,14 @@ __global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> 
     store_node<Q, ST, PHASE>(A, static_cast<typename CD::S*>(A.f), n, x, y, z, fb, h,
                              (1u << Q) - 1u);
   }
+}
+
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_nee(LatticeArgs<typename Codec<ST>::C> A,
+                                             NeeArgs<typename Codec<ST>::C> E,
+                                             const int* __restrict__ nodes, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    nee_node<Q, ST, PHASE>(A, E, (unsigned)nodes[i]);
 }
 
 template <int Q, int ST>
@@ -1169,6 +1176,81 @@ hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const B
     batch_launch_m<18, ST_F32>(mode, forced, L, s);
   else if (q == 18 && storage == ST_F16)
     batch_launch_m<18, ST_F16>(mode, forced, L, s);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// The velocity / pressure / node-layer symmetry pass of a batched substep:
+// one thread per boundary node of the class's members.  A thread finds its
+// member as the last one whose first boundary index is <= its own (members
+// without such faces own an empty range) and runs the single-lattice pass
+// for that node, with the member's time level, force and face pressures of
+// the level just reached (host-computed rows, the same floats as for a
+// single lattice), so a member gives the same bits alone, in any mix, and
+// as a single lattice.
+__device__ __forceinline__ int find_nee_member(const BatchMember* __restrict__ ms, int nm,
+                                               long long i) {
+  int lo = 0, hi = nm - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ms[mid].nee_begin <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_batch_nee(const BatchMember* __restrict__ ms, int nm,
+                                                   const float* __restrict__ ntab, int substep,
+                                                   long long total) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const BatchMember& m = ms[find_nee_member(ms, nm, i)];
+    const long long j = i - m.nee_begin;
+    if (j < 0 || j >= m.nee_count) continue;
+    const int own = substep - m.skip;
+    if (own < 0 || own >= m.steps) continue;
+    LatticeArgs<float> A = m.a;
+    A.tstep += (unsigned)(own + 1);
+    const float* row = ntab + m.ntab_off + 9LL * own;
+    A.F[0] = row[0];
+    A.F[1] = row[1];
+    A.F[2] = row[2];
+    NeeArgs<float> E = m.e;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) E.p[f] = row[3 + f];
+    nee_node<Q, ST, PHASE>(A, E, (unsigned)m.nee_nodes[j]);
+  }
+}
+
+template <int Q, int ST>
+static void batch_nee_q(int phase, const BatchMember* ms, int nm, const float* ntab, int substep,
+                        long long total, hipStream_t s) {
+  const int nb = aux_blocks(total);
+  if (phase == 0)
+    hipLaunchKernelGGL((k_batch_nee<Q, ST, 0>), dim3(nb), dim3(256), 0, s, ms, nm, ntab, substep,
+                       total);
+  else
+    hipLaunchKernelGGL((k_batch_nee<Q, ST, 1>), dim3(nb), dim3(256), 0, s, ms, nm, ntab, substep,
+                       total);
+}
+
+hipError_t launch_batch_nee(int q, int storage, int phase, const BatchMember* members,
+                            int nmembers, const float* ntab, int substep, long long total,
+                            hipStream_t s) {
+  clear_stale_error();
+  if (total <= 0 || nmembers <= 0) return hipSuccess;
+  if (q == 14 && storage == ST_F32)
+    batch_nee_q<14, ST_F32>(phase, members, nmembers, ntab, substep, total, s);
+  else if (q == 14 && storage == ST_F16)
+    batch_nee_q<14, ST_F16>(phase, members, nmembers, ntab, substep, total, s);
+  else if (q == 18 && storage == ST_F32)
+    batch_nee_q<18, ST_F32>(phase, members, nmembers, ntab, substep, total, s);
+  else if (q == 18 && storage == ST_F16)
+    batch_nee_q<18, ST_F16>(phase, members, nmembers, ntab, substep, total, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -117,6 +117,13 @@ struct BatchMember {
   int forced;
   int flat;                // 1: tile lt = nodes [256 lt, 256 lt + 256) in linear order
   FastDiv fd_nx, fd_ny;    // flat tiles: node index -> (x, y, z)
+  // velocity / pressure / node-layer symmetry faces (nee_count > 0 only)
+  const int* nee_nodes;    // the member's boundary node list (device)
+  int nee_count;
+  long long nee_begin;     // first index of its nodes in its class's boundary pass
+  long long ntab_off;      // float offset of its boundary rows: per own step,
+                           // F at the level reached (3) and the face pressures (6)
+  NeeArgs<float> e;        // face kinds and velocities (e.p comes from the rows)
 };
 // Tiles of one member run one after the other by one workgroup of a large
 // batched launch.
@@ -144,6 +151,14 @@ struct BatchLaunch {
 };
 hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const BatchLaunch& L,
                               hipStream_t stream);
+// The velocity / pressure / node-layer symmetry pass of substep `substep`
+// for the members[0..nmembers) of one launch class (same q and storage),
+// right after that class's step launch: `total` boundary nodes, member m's
+// at [m.nee_begin, m.nee_begin + m.nee_count); phase is the AA layout after
+// the step (1 after an even step, 0 after an odd one).
+hipError_t launch_batch_nee(int q, int storage, int phase, const BatchMember* members,
+                            int nmembers, const float* ntab, int substep, long long total,
+                            hipStream_t stream);
 // Monitor pass 1 of every member: partial sums into partial[3*blocks of
 // member]; member m writes at partial + 3*pofs[m].
 hipError_t launch_batch_monitor(const BatchMember* members, int nmembers, void* const* snaps,

@@ -858,6 +858,8 @@ struct lbm_batch {
   size_t d_chunks_cap = 0;
   float* d_ftab = nullptr;
   size_t d_ftab_cap = 0;
+  float* d_ntab = nullptr;   // boundary rows (9 floats per member step)
+  size_t d_ntab_cap = 0;
   // pinned host staging + the event that says it may be reused
   BatchMember* h_members = nullptr;
   size_t h_members_cap = 0;
@@ -865,6 +867,8 @@ struct lbm_batch {
   size_t h_chunks_cap = 0;
   float* h_ftab = nullptr;
   size_t h_ftab_cap = 0;
+  float* h_ntab = nullptr;
+  size_t h_ntab_cap = 0;
   hipEvent_t staged = nullptr;
   // monitor staging
   char* d_mon = nullptr;
@@ -927,8 +931,6 @@ int lbm_batch_add(lbm_batch* b, lbm_ctx* c, long long budget) {
     return bfail(b, LBM_EINVAL, "batched members must store LBM_F32 or LBM_F16DEV");
   if (c->stream != b->stream) return bfail(b, LBM_EINVAL, "member stream differs from batch stream");
   if (c->spec.collision != LBM_MRT) return bfail(b, LBM_EINVAL, "batched members use LBM_MRT");
-  if (c->nee_count > 0)
-    return bfail(b, LBM_EINVAL, "velocity / pressure faces are not batched (single lattices only)");
   b->members.push_back(Member{c, budget, 0, 0});
   c->batch = b;
   return LBM_OK;
@@ -976,13 +978,14 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   // active members and their step counts for this call
   std::vector<int> act;
   long long nmax = 0;
-  size_t ftab_rows = 0;
+  size_t ftab_rows = 0, ntab_rows = 0;
   for (size_t i = 0; i < b->members.size(); ++i) {
     const long long k = std::min(n, b->members[i].remaining);
     if (k <= 0) continue;
     act.push_back((int)i);
     nmax = std::max(nmax, k);
     if (b->members[i].ctx->forced) ftab_rows += (size_t)k;
+    if (b->members[i].ctx->nee_count > 0) ntab_rows += (size_t)k;
   }
   if (act.empty()) return LBM_OK;
   // One specialised launch per (q, storage) class and step.  For n >= 2 the
@@ -1001,7 +1004,7 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return cls(x) < cls(y); });
   const int nm = (int)act.size();
   int cls_off[NG] = {}, cls_cnt[NG] = {}, cls_forced[NG] = {};
-  long long cls_tiles[NG] = {}, cls_steps[NG] = {};
+  long long cls_tiles[NG] = {}, cls_steps[NG] = {}, cls_nee[NG] = {};
   // chunks (large classes only): a member's tiles in runs of kBatchChunk,
   // grouped by class
   auto member_tiles = [&](int i) {
@@ -1028,8 +1031,10 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   if (!rc) rc = grow_dev(b, b->d_chunks, b->d_chunks_cap, std::max<long long>(nchunks, 1));
   if (!rc) rc = grow_host(b, b->h_ftab, b->h_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
   if (!rc) rc = grow_dev(b, b->d_ftab, b->d_ftab_cap, std::max<size_t>(3 * ftab_rows, 3));
+  if (!rc) rc = grow_host(b, b->h_ntab, b->h_ntab_cap, std::max<size_t>(9 * ntab_rows, 9));
+  if (!rc) rc = grow_dev(b, b->d_ntab, b->d_ntab_cap, std::max<size_t>(9 * ntab_rows, 9));
   if (rc) return rc;
-  size_t frow = 0;
+  size_t frow = 0, nrow = 0;
   long long chunk = 0;
   for (int j = 0; j < nm; ++j) {
     Member& m = b->members[act[j]];
@@ -1084,6 +1089,31 @@ int lbm_batch_step(lbm_batch* b, long long n) {
       }
       frow += (size_t)k;
     }
+    // velocity / pressure / node-layer symmetry faces: after each of its
+    // steps, at the level reached, the force and face pressures the
+    // single-lattice step uses there
+    bm.nee_nodes = c->nee_nodes;
+    bm.nee_count = c->nee_count;
+    bm.nee_begin = cls_nee[k_cls];
+    bm.ntab_off = 9LL * (long long)nrow;
+    bm.e = c->e32;
+    if (c->nee_count > 0) {
+      cls_nee[k_cls] += c->nee_count;
+      for (long long s = 0; s < k; ++s) {
+        const long long lev = c->t + s + 1;
+        double F[3];
+        force_at(c->spec, lev, F);
+        float* row = b->h_ntab + 9 * (nrow + s);
+        for (int d = 0; d < 3; ++d) row[d] = (float)F[d];
+        for (int f = 0; f < 6; ++f) {
+          double pf = c->spec.face_p[f];
+          if (c->spec.FT > 0.0)
+            pf += c->spec.face_pA[f] * std::cos(2.0 * M_PI * (double)lev / c->spec.FT);
+          row[3 + f] = (float)pf;
+        }
+      }
+      nrow += (size_t)k;
+    }
   }
   for (int k = 0; k < NG; ++k)
     if (cls_tiles[k] >= (1LL << 30)) return bfail(b, LBM_EINVAL, "too many tiles in one batch");
@@ -1095,6 +1125,9 @@ int lbm_batch_step(lbm_batch* b, long long n) {
                            hipMemcpyHostToDevice, b->stream));
   if (frow)
     BHIP(b, hipMemcpyAsync(b->d_ftab, b->h_ftab, 3 * frow * sizeof(float), hipMemcpyHostToDevice,
+                           b->stream));
+  if (nrow)
+    BHIP(b, hipMemcpyAsync(b->d_ntab, b->h_ntab, 9 * nrow * sizeof(float), hipMemcpyHostToDevice,
                            b->stream));
   BHIP(b, hipEventRecord(b->staged, b->stream));
   nmax = 0;
@@ -1113,6 +1146,10 @@ int lbm_batch_step(lbm_batch* b, long long n) {
       BHIP(b, launch_batch_group((k & 2) ? 18 : 14, (k & 1) ? ST_F16 : ST_F32,
                                  odd ? MODE_AA_ODD : MODE_AA_EVEN, cls_forced[k] != 0, L,
                                  b->stream));
+      if (cls_nee[k] > 0)
+        BHIP(b, launch_batch_nee((k & 2) ? 18 : 14, (k & 1) ? ST_F16 : ST_F32, odd ? 0 : 1,
+                                 b->d_members + cls_off[k], cls_cnt[k], b->d_ntab, (int)s,
+                                 cls_nee[k], b->stream));
     }
   for (int j = 0; j < nm; ++j) {
     Member& m = b->members[act[j]];
@@ -1214,10 +1251,12 @@ int lbm_batch_destroy(lbm_batch* b) {
   if (b->d_members) (void)hipFree(b->d_members);
   if (b->d_chunks) (void)hipFree(b->d_chunks);
   if (b->d_ftab) (void)hipFree(b->d_ftab);
+  if (b->d_ntab) (void)hipFree(b->d_ntab);
   if (b->d_mon) (void)hipFree(b->d_mon);
   if (b->h_members) (void)hipHostFree(b->h_members);
   if (b->h_chunks) (void)hipHostFree(b->h_chunks);
   if (b->h_ftab) (void)hipHostFree(b->h_ftab);
+  if (b->h_ntab) (void)hipHostFree(b->h_ntab);
   if (b->staged) (void)hipEventDestroy(b->staged);
   delete b;
   return LBM_OK;

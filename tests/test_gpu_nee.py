@@ -8,6 +8,7 @@ and node-layer symmetry planes (Eq. (z05symmetry) on the node-based grid):
   periodic axes (FP64 1e-13 of max|f|; FP32 / FP16 at their storage
   tolerances);
 * AA == AB bit for bit;
+* in a batch, mixed with other members, bit for bit as single lattices;
 * the 49 x 49 x 25 half cavity with a node-layer symmetry plane equals the
   lower half of the full 49^3 cavity;
 * the paper's own numbers: every entry of Table 1 (steady Poiseuille,
@@ -109,15 +110,40 @@ def test_aa_equals_ab_bit_exact(q, storage, setup):
     assert np.array_equal(out["aa"], out["ab"])
 
 
-def test_batches_reject_velocity_and_pressure_faces():
-    q = 14
-    lat = lbm.Lattice(q, 9, 7, 7, svec(q, 1.2), faces=NEE_FACES, face_p={"-x": 0.001},
-                      storage="f32")
-    b = lbm.Batch(lat.stream)
-    with pytest.raises(lbm.LbmError):
-        b.add(lat, 10)
+@pytest.mark.parametrize("storage", ("f32", "f16dev"))
+def test_batched_faces_equal_single_lattices_bit_exact(storage):
+    """Every set-up above, both models, advanced as single lattices (lbm_step)
+    and as members of one batch together with a plain wall cavity: the
+    populations agree bit for bit.  The batch runs in uneven calls (5, 1, 4,
+    3 steps) and two members start at the other AA parity, so members sit
+    out substeps and single-step calls take the parity into the class."""
+    singles, members = [], []
+    for q in (14, 18):
+        for k, setup in enumerate(sorted(SETUPS)):
+            for group in (singles, members):
+                lat, _ = make(q, setup, storage, "aa", seed=11 + k)
+                if k in (1, 4):
+                    lat.step(1)
+                group.append(lat)
+        for group in (singles, members):
+            lat = lbm.Lattice(q, 12, 10, 9, rates(q), storage=storage, pattern="aa",
+                              faces=("wall",) * 6, wall_u={"+z": (0.05, 0.0, 0.0)})
+            lat.set_f(inputs.random_populations(q, 12, 10, 9, seed=40 + q))
+            group.append(lat)
+    b = lbm.Batch(members[0].stream)
+    for lat in members:
+        b.add(lat, 10 ** 6)
+    for n in (5, 1, 4, 3):
+        b.step(n)
     b.close()
-    lat.close()
+    for s_lat, m_lat in zip(singles, members):
+        # members out of parity sit out a substep: step each single lattice
+        # to its member's level
+        assert m_lat.time >= 10
+        s_lat.step(m_lat.time - s_lat.time)
+        assert np.array_equal(s_lat.get_f(), m_lat.get_f()), (s_lat.q, s_lat.nx, s_lat.ny, s_lat.nz)
+    for lat in singles + members:
+        lat.close()
 
 
 def run_poiseuille(dx, inv_tau, storage="f64"):
