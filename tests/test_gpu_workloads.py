@@ -1,4 +1,4 @@
-"""The duct workloads at their configured sizes on the GPU, against the FP64
+"""The workloads at their configured sizes on the GPU, against the FP64
 oracle and the paper's analytic series (Sec. 4.1, 4.2).
 
 * D3Q14 FP64, 16x16 cross-section (half-way walls), 32 periodic, nu = 0.1,
@@ -10,6 +10,9 @@ oracle and the paper's analytic series (Sec. 4.1, 4.2).
   GPU runs vs the FP64 oracle and vs the series at T/4, T/2, 3T/4, T of the
   last period.  The flow is x-invariant, and so is the arithmetic at every
   x, so the oracle runs one x-slice (nx = 1) and is compared at every x.
+* The 128^3 D3Q18 lid-driven cavity (Re = 1000) for its 20,000 steps in
+  FP32 and FP16 deviations against the FP64 path, and the FP64 path against
+  the oracle on a 64^3 proxy of the same viscosity for 2,000 steps.
 """
 import numpy as np
 import pytest
@@ -133,3 +136,54 @@ def test_half_cavity_with_symmetry_plane_fp32(q):
     err = np.max(np.abs(low - uh)) / np.max(np.abs(low))
     print("half cavity q=%d: max|u_half - u_full|/max|u| %.2e" % (q, err))
     assert err <= 1e-5
+
+
+def _rel(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def test_headline_cavity_fp32_and_fp16_against_fp64_after_20000_steps():
+    """The 128^3 D3Q18 lid-driven cavity at Re = 1000 (lid 0.1, nu = 0.0128),
+    the measured workload, run for its 20,000 steps in FP32 and FP16
+    deviations against the FP64 path (itself equal to the oracle per step to
+    1e-13, and on the 64^3 proxy below over 2,000 steps).  Measured: FP32
+    rel. L2 1.3e-7 (u), 1.1e-6 (p); FP16 2.8e-4 (u), 7.5e-3 (p, a field
+    three orders below u^2 here)."""
+    from paper_1503_03337_amd import params
+    n = 128
+    cfg = params.cavity(18, n, 1000.0, lid=0.1)
+    res = {}
+    for storage in ("f64", "f32", "f16dev"):
+        lat = lbm.Lattice(18, n, n, n, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"],
+                          storage=storage, pattern="aa")
+        lat.step(20000)
+        p, u = lat.macros()
+        res[storage] = (p - p.mean(), u)
+        lat.close()
+    p64, u64 = res["f64"]
+    assert _rel(res["f32"][1], u64) <= 1e-5 and _rel(res["f32"][0], p64) <= 1e-5
+    assert _rel(res["f16dev"][1], u64) <= 2e-3 and _rel(res["f16dev"][0], p64) <= 5e-2
+    print("128^3 cavity, 20000 steps, rel L2 vs FP64: FP32 u %.2e p %.2e, FP16 u %.2e p %.2e"
+          % (_rel(res["f32"][1], u64), _rel(res["f32"][0], p64),
+             _rel(res["f16dev"][1], u64), _rel(res["f16dev"][0], p64)))
+
+
+def test_cavity_64_fp64_equals_oracle_after_2000_steps():
+    """The same cavity physics on a 64^3 proxy (nu = 0.0128, Re = 500 on the
+    shorter lid): the FP64 GPU path against the FP64 oracle after 2,000
+    steps from rest."""
+    from paper_1503_03337_amd import params
+    m = 64
+    cfg = params.cavity(18, m, 500.0, lid=0.1)
+    lat = lbm.Lattice(18, m, m, m, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"],
+                      storage="f64", pattern="aa")
+    pr = R.problem(18, m, m, m, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"])
+    f = R.init_eq(pr)
+    lat.set_f(f)
+    g = R.run(pr, f, 0, 2000)
+    lat.step(2000)
+    assert _rel(lat.get_f(), g) <= 1e-12
+    p, u = lat.macros()
+    pr_, ur = R.macros(pr, g, 2000)
+    assert _rel(u, ur) <= 1e-12
+    lat.close()
