@@ -7,9 +7,11 @@ oscillating), steady or oscillating body forces, random rates, both models,
 both memory patterns.
 
 * FP64: the GPU step equals the oracle element-wise (1e-13 of max|f|) after
-  1 and 4 steps (both AA parities).
-* FP32 AA: the same configurations advanced together in one batch, in
-  uneven calls, give bit for bit the populations of single lattices.
+  1 and 4 steps (both AA parities); every fourth configuration uses the
+  LBGK collision, against the oracle's MRT step with all rates equal.
+* FP32 and FP16-deviation AA: the same configurations advanced together in
+  one batch, in uneven calls, give bit for bit the populations of single
+  lattices.
 """
 import numpy as np
 import pytest
@@ -65,9 +67,15 @@ def configs():
 def test_random_config_fp64_matches_oracle(i):
     q, dims, s, kw = configs()[i]
     pattern = "aa" if i % 2 == 0 else "ab"
-    print("config %d: q=%d dims=%s faces=%s pattern=%s FT=%g" % (i, q, dims, kw["faces"], pattern,
-                                                                kw["FT"]), flush=True)
-    lat = lbm.Lattice(q, *dims, s, storage="f64", pattern=pattern, **kw)
+    collision = "mrt"
+    if i % 4 == 3:
+        # every fourth: the LBGK collision, against the oracle's MRT step with
+        # every rate equal (the paper's reduction)
+        collision = "bgk"
+        s = np.full(q, s[8])
+    print("config %d: q=%d dims=%s faces=%s pattern=%s %s FT=%g"
+          % (i, q, dims, kw["faces"], pattern, collision, kw["FT"]), flush=True)
+    lat = lbm.Lattice(q, *dims, s, storage="f64", pattern=pattern, collision=collision, **kw)
     pr = R.problem(q, *dims, s, **kw)
     lat.set_f(inputs.random_populations(q, *dims, seed=100 + i))
     f = lat.get_f()
@@ -81,11 +89,12 @@ def test_random_config_fp64_matches_oracle(i):
     lat.close()
 
 
-def test_random_configs_batched_equal_single_fp32():
+@pytest.mark.parametrize("storage", ("f32", "f16dev"))
+def test_random_configs_batched_equal_single(storage):
     singles, members = [], []
     for i, (q, dims, s, kw) in enumerate(configs()):
         for group in (singles, members):
-            lat = lbm.Lattice(q, *dims, s, storage="f32", pattern="aa", **kw)
+            lat = lbm.Lattice(q, *dims, s, storage=storage, pattern="aa", **kw)
             lat.set_f(inputs.random_populations(q, *dims, seed=300 + i))
             if i % 3 == 0:
                 lat.step(1)
