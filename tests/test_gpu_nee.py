@@ -13,8 +13,8 @@ and node-layer symmetry planes (Eq. (z05symmetry) on the node-based grid):
   lower half of the full 49^3 cavity;
 * the paper's own numbers: every entry of Table 1 (steady Poiseuille,
   Sec. 4.1, dx = 1/8 .. 1/64, 1/tau = 0.8, 1.0, 1.3) and Table 2
-  (pulsatile, Sec. 4.2, dx = 1/20 .. 1/80, four phases) to the last
-  printed digit, against the analytic series.
+  (pulsatile, Sec. 4.2, dx = 1/20 .. 1/80, four phases) within one unit
+  of the last printed digit, against the analytic series.
 """
 import numpy as np
 import pytest

@@ -6,7 +6,7 @@ pressure faces), the boundary scheme the paper applies in all of Sec. 4.
   and every pressure-face node exactly the face pressure at the new level;
 * the paper's own numbers: the steady pressure-driven Poiseuille flow of
   Sec. 4.1 reproduces Table 1 and the pulsatile flow of Sec. 4.2 Table 2,
-  to the last printed digit, against the analytic series of the paper
+  within one unit of the last printed digit, against the analytic series of the paper
   (Eq. for u(y, z) in Sec. 4.1, Eq. (wa) in Sec. 4.2).
 """
 import numpy as np
