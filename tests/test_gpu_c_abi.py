@@ -1,6 +1,8 @@
 """The C ABI used from plain C (tests/c_abi/lid_cavity.c: include/lbm.h and
 liblbm.so only, the library's own device memory, the null stream), run as a
-child process; its macroscopic fields against the FP64 oracle."""
+child process; its macroscopic fields against the FP64 oracle, and its
+batch (a pressure-driven duct and a lid cavity, one with a step budget)
+bit-identical to single runs, checked by the program itself."""
 import os
 import subprocess
 
@@ -21,6 +23,8 @@ def test_plain_c_lid_cavity_matches_oracle(tmp_path):
     run = subprocess.run([exe, str(out)], capture_output=True, text=True, timeout=120)
     assert run.returncode == 0, run.stderr
     print(run.stdout.strip())
+    assert "bit-identical to single runs" in run.stdout
+    assert "duct t=17, cavity t=12" in run.stdout
     nx, ny, nz, N = 12, 10, 8, 12 * 10 * 8
     data = np.fromfile(out, dtype=np.float64)
     assert data.size == 4 * N
