@@ -269,11 +269,16 @@ int lbm_destroy(lbm_ctx* ctx);
  * class covering all of them (plus one launch for the velocity / pressure /
  * node-layer symmetry pass when any member of the class has such faces); each
  * member keeps its own time level, parity and populations, and its result
- * is bit-identical to running it alone in a batch.  Members must share the
- * batch's stream.  Members can be added and removed between calls
- * (continuous batching).  Each member has a step budget: lbm_batch_step
- * advances it by min(n, remaining budget). */
+ * is bit-identical to running it alone in a batch and to stepping it with
+ * lbm_step.  Members must share the batch's stream.  Members can be added
+ * and removed between calls (continuous batching).  Each member has a step
+ * budget: lbm_batch_step advances it by min(n, remaining budget).  The batch
+ * does not own its members: destroying a member removes it, and destroying
+ * the batch leaves the members usable on their own. */
 int lbm_batch_create(lbm_batch** out, void* stream);
+/* LBM_EINVAL (message in lbm_batch_last_error) for a context that is
+ * already in a batch, not LBM_AA, stored as LBM_F64, on another stream, or
+ * using the LBGK collision; step_budget >= 0. */
 int lbm_batch_add(lbm_batch* b, lbm_ctx* ctx, long long step_budget);
 int lbm_batch_remove(lbm_batch* b, lbm_ctx* ctx);
 /* Mapping of a member's nodes to workgroups: a tx x ty tile (tx*ty <= 256
