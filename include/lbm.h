@@ -213,8 +213,11 @@ int lbm_macros_device(lbm_ctx* ctx, double* p_dev, double* u_dev);
  *   R = sum_n sum_k |u_k(n,t) - u_k(n,t-L)| / (L sum_n sum_k |u_k(n,t)|)
  * with L the steps since the previous snapshot (the steady-state criteria
  * Eqs. (sc), (cr), (cavity_creterion) for lag L, per step).  +inf when
- * sum|u| = 0 or before a second snapshot.  LBM_ENONFINITE if the monitor saw
- * a non-finite value.  Synchronises the stream. */
+ * sum|u| = 0 or when the monitor had no earlier snapshot of the current state
+ * (its first run, or the first after lbm_set_f, lbm_init_fields or
+ * lbm_set_time).  LBM_ENONFINITE if the monitor saw a non-finite value in u,
+ * the mass or (with an earlier snapshot) the change of u.  Synchronises the
+ * stream. */
 int lbm_residual(lbm_ctx* ctx, double* r);
 
 /* Mass M = sum_n P(n) = sum_n sum_a f_a(n) (FP64) from the last monitor run;

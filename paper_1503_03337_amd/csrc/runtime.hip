@@ -677,11 +677,17 @@ int lbm_residual(lbm_ctx* c, double* r) {
   if (!c->mon_ran) return fail(c, LBM_ESTATE, "the monitor has not run");
   int rc = fetch_monitor(c);
   if (rc) return rc;
-  if (!std::isfinite(c->mon[0]) || !std::isfinite(c->mon[1]) || !std::isfinite(c->mon[2])) {
+  // Without an earlier snapshot of this state (lag 0) the difference sum was
+  // taken against whatever the snapshot buffer held (fresh memory, or a
+  // state replaced since) and means nothing: only sum|u| and the mass
+  // speak for the current populations then.
+  const bool lagged = c->mon_lag > 0;
+  if ((lagged && !std::isfinite(c->mon[0])) || !std::isfinite(c->mon[1]) ||
+      !std::isfinite(c->mon[2])) {
     *r = std::numeric_limits<double>::quiet_NaN();
     return fail(c, LBM_ENONFINITE, "monitor found a non-finite value");
   }
-  if (c->mon_lag <= 0 || !(c->mon[1] > 0.0))
+  if (!lagged || !(c->mon[1] > 0.0))
     *r = std::numeric_limits<double>::infinity();
   else
     *r = c->mon[0] / ((double)c->mon_lag * c->mon[1]);

@@ -170,6 +170,32 @@ def test_batch_monitor_matches_single_monitor():
         lat.close()
 
 
+
+def test_batch_monitor_first_residual_ignores_the_stale_snapshot():
+    """As for single lattices: the batch monitor's first pass over a state
+    gives residual +inf whatever the snapshot buffer held (here the NaN
+    velocity of a replaced state); a NaN in the state itself is reported."""
+    lat = build(0, 610, monitor_every=1000)
+    f = lat.get_f()
+    bad = f.copy()
+    bad[2, 1, 1, 1] = np.nan
+    lat.set_f(bad)
+    b = lbm.Batch(lat.stream)
+    b.add(lat, 50)
+    b.monitor()
+    with pytest.raises(lbm.LbmError) as e:
+        lat.residual()
+    assert e.value.code == -4
+    lat.set_f(f)
+    b.monitor()
+    assert lat.residual() == np.inf
+    b.step(4)
+    b.monitor()
+    r = lat.residual()
+    assert np.isfinite(r) and r > 0
+    b.close()
+    lat.close()
+
 def test_batch_rejects_unsupported_members():
     q = 18
     lat = lbm.Lattice(q, 8, 8, 8, svec(q, 1.2), storage="f64")

@@ -234,6 +234,54 @@ def test_half_cavity_node_symmetry_equals_full_cavity():
     assert err <= 1e-12
 
 
+def run_cavity_re3200(n, steps, collision, storage):
+    """Sec. 4.3 at Re = 3200: the half cavity on the paper's node-based grid
+    n x n x (n + 1)/2 (velocity walls, node-layer symmetry plane), lid 0.1
+    (c = 10), nu = U L / Re in lattice units, tau = 0.5045 at n = 49 and
+    0.509 at n = 97.  MRT uses the paper's rates; LBGK relaxes every moment
+    at 1/tau, which on the 14 moving velocities is He's iD3Q15 LBGK (its
+    rest population does not enter the update of the others).  Returns the
+    time level at which the monitor found a non-finite value, or None and
+    max|u| / U after `steps` steps."""
+    q, U = 14, 0.1
+    nu = U * (n - 1) / 3200.0
+    sn = 1.0 / (3 * nu + 0.5)
+    s = svec(q, sn) if collision == "mrt" else np.full(q, sn)
+    lat = lbm.Lattice(q, n, n, (n + 1) // 2, s, faces=("velocity",) * 5 + ("symmetry_node",),
+                      wall_u={"+x": (0.0, U, 0.0)}, storage=storage, pattern="aa",
+                      monitor_every=1000, collision=collision)
+    try:
+        while lat.time < steps:
+            lat.step(1000)
+            lat.residual()
+    except lbm.LbmError as e:
+        assert e.code == -4
+        t = lat.time
+        lat.close()
+        return t, None
+    umax = float(np.max(np.abs(lat.macros()[1]))) / U
+    lat.close()
+    return None, umax
+
+
+@pytest.mark.parametrize("storage", ("f64", "f32"))
+def test_re3200_cavity_mrt_stable_where_lbgk_diverges(storage):
+    """Sec. 4.3's stability comparison: at Re = 3200 on 49 x 49 x 25 the
+    iD3Q14 MRT model runs the paper's 25,000 steps while the LBGK model
+    blows up; on 97 x 97 x 49 both run the paper's 50,000 steps.  A stable
+    run keeps every velocity within the lid speed."""
+    out = {}
+    for n, steps in ((49, 25000), (97, 50000)):
+        for coll in ("mrt", "bgk"):
+            out[n, coll] = run_cavity_re3200(n, steps, coll, storage)
+    print("Re 3200 (%s): %s" % (storage, out))
+    for key in ((49, "mrt"), (97, "mrt"), (97, "bgk")):
+        t_bad, umax = out[key]
+        assert t_bad is None and umax <= 1.0 + 1e-6, (key, out[key])
+    t_bad, _ = out[49, "bgk"]
+    assert t_bad is not None and t_bad <= 25000
+
+
 @pytest.mark.parametrize("dp", ("0.001", "0.005", "0.01", "0.02", "0.05"))
 def test_table3_id3q14_column_reproduced(dp):
     """Table 3, iD3Q14 column (pulsatile, 41 x 21 x 21, dt = 0.05, c = 1,

@@ -323,6 +323,34 @@ def test_nonfinite_is_reported():
     lat.close()
 
 
+
+@pytest.mark.parametrize("storage", ("f64", "f32", "f16dev"))
+def test_first_residual_of_a_state_ignores_the_stale_snapshot(storage):
+    """The monitor's first pass over a state (after create, set_f,
+    init_fields or set_time) has nothing to difference against: the
+    residual is +inf, and only u and the mass decide LBM_ENONFINITE, not
+    whatever the snapshot buffer held.  Here it holds the NaN velocity of a
+    replaced state; fresh device memory can hold any bit pattern as well,
+    which once made an FP32 lattice report a finite state as non-finite."""
+    q, dims = 14, (12, 10, 8)
+    lat = lbm.Lattice(q, *dims, rates(q), faces=FACESETS["cavity"], storage=storage)
+    f = inputs.random_populations(q, *dims, seed=12)
+    bad = f.copy()
+    bad[1, 2, 3, 4] = np.nan
+    lat.set_f(bad)
+    lat.monitor()
+    with pytest.raises(lbm.LbmError) as e:
+        lat.residual()
+    assert e.value.code == -4
+    lat.set_f(f)
+    lat.monitor()
+    assert lat.residual() == np.inf
+    lat.step(4)
+    lat.monitor()
+    r = lat.residual()
+    assert np.isfinite(r) and r > 0
+    lat.close()
+
 # ---- full-size workload: 128^3 lid-driven cavity, D3Q18, FP32, AA ---------
 
 def cavity128(q=18, storage="f32"):
