@@ -136,7 +136,8 @@ typedef enum { LBM_MRT = 0, LBM_BGK = 1 } lbm_collision;
 typedef enum {
   LBM_OK = 0,
   LBM_EINVAL = -1,     /* bad argument: q, dims < 1, N >= 2^31, s_k outside [0,2),
-                          unpaired periodic faces, |u_w| >= 0.3, bad storage ... */
+                          unpaired periodic faces, |u_w| >= 0.3, bad storage,
+                          a non-finite F0, FA, FT, p0, u0 or face pressure ... */
   LBM_ENOMEM = -2,     /* footprint above dev_buf_bytes or hipMalloc failure */
   LBM_EDEVICE = -3,    /* a HIP call failed (message in lbm_last_error) */
   LBM_ENONFINITE = -4, /* a monitor found a non-finite mass or velocity */

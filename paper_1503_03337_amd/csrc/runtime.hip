@@ -107,7 +107,10 @@ std::string validate(int model, int nx, int ny, int nz, const double* s, const l
   }
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(sp->F0[d]) || !std::isfinite(sp->FA[d])) return "force must be finite";
+  if (!std::isfinite(sp->FT)) return "FT must be finite";
   if (!std::isfinite(sp->p0)) return "p0 must be finite";
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(sp->u0[d])) return "u0 must be finite";
   if (s) {
     for (int k = 0; k < model; ++k)
       if (!(s[k] >= 0.0 && s[k] < 2.0)) return "relaxation rates must lie in [0, 2)";

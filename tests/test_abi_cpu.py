@@ -63,6 +63,8 @@ def test_footprint_without_device():
     dict(faces=("wall",) * 5 + (-1,)),
     dict(nx=2, faces=("pressure", "pressure") + ("velocity",) * 4),
     dict(faces=("pressure", "wall") + ("wall",) * 4, face_p={"-x": float("nan")}),
+    dict(u0=(0.0, float("nan"), 0.0)), dict(FT=float("nan")), dict(FT=float("inf")),
+    dict(p0=float("inf")), dict(F0=(float("nan"), 0.0, 0.0)),
 ])
 def test_footprint_rejects_invalid(bad):
     from paper_1503_03337_amd import lbm
