@@ -83,7 +83,7 @@ def test_fp64_matches_oracle(q, pattern, setup):
 
 @pytest.mark.parametrize("q", (14, 18))
 @pytest.mark.parametrize("storage", ("f32", "f16dev"))
-@pytest.mark.parametrize("setup", ("duct", "corners"))
+@pytest.mark.parametrize("setup", sorted(SETUPS))
 def test_reduced_storage_matches_oracle(q, storage, setup):
     lat, pr = make(q, setup, storage, "aa")
     f = lat.get_f()

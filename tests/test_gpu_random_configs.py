@@ -11,7 +11,9 @@ both memory patterns.
   LBGK collision, against the oracle's MRT step with all rates equal.
 * FP32 and FP16-deviation AA: the same configurations advanced together in
   one batch, in uneven calls, give bit for bit the populations of single
-  lattices.
+  lattices, and those equal the oracle run from the same (rounded) start
+  within the storage's rounding: relative L2 1e-6 in FP32, one FP16 rounding
+  per value and step (2 sqrt(steps) 2^-10) for FP16 deviations.
 """
 import numpy as np
 import pytest
@@ -91,11 +93,14 @@ def test_random_config_fp64_matches_oracle(i):
 
 @pytest.mark.parametrize("storage", ("f32", "f16dev"))
 def test_random_configs_batched_equal_single(storage):
-    singles, members = [], []
-    for i, (q, dims, s, kw) in enumerate(configs()):
+    cfgs = configs()
+    singles, members, starts = [], [], []
+    for i, (q, dims, s, kw) in enumerate(cfgs):
         for group in (singles, members):
             lat = lbm.Lattice(q, *dims, s, storage=storage, pattern="aa", **kw)
             lat.set_f(inputs.random_populations(q, *dims, seed=300 + i))
+            if group is singles:
+                starts.append(lat.get_f())  # the start as stored (rounded)
             if i % 3 == 0:
                 lat.step(1)
             group.append(lat)
@@ -105,8 +110,18 @@ def test_random_configs_batched_equal_single(storage):
     for n in (3, 1, 2):
         b.step(n)
     b.close()
+    worst = 0.0
     for i, (s_lat, m_lat) in enumerate(zip(singles, members)):
         s_lat.step(m_lat.time - s_lat.time)
-        assert np.array_equal(s_lat.get_f(), m_lat.get_f()), i
+        g = m_lat.get_f()
+        assert np.array_equal(s_lat.get_f(), g), i
+        q, dims, s, kw = cfgs[i]
+        steps = m_lat.time
+        f = R.run(R.problem(q, *dims, s, **kw), starts[i], 0, steps)
+        err = np.linalg.norm(g - f) / np.linalg.norm(f)
+        tol = 1e-6 if storage == "f32" else 2 * np.sqrt(steps) * 2.0 ** -10
+        assert err <= tol, (i, steps, err)
+        worst = max(worst, err / tol)
+    print("%s: worst error / tolerance against the oracle %.3f" % (storage, worst))
     for lat in singles + members:
         lat.close()
