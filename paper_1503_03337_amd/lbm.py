@@ -343,7 +343,9 @@ class Batch:
         self.members.append(lat)
 
     def remove(self, lat):
-        self._chk(lib().lbm_batch_remove(self.h, lat.h), "lbm_batch_remove")
+        # a closed lattice already left the batch when it was destroyed
+        if lat.h is not None:
+            self._chk(lib().lbm_batch_remove(self.h, lat.h), "lbm_batch_remove")
         self.members.remove(lat)
 
     def set_tile(self, lat, tx, ty):

@@ -196,6 +196,27 @@ def test_batch_monitor_first_residual_ignores_the_stale_snapshot():
     b.close()
     lat.close()
 
+
+def test_closing_a_member_leaves_the_batch():
+    """Destroying a member removes it from its batch; the batch goes on with
+    the others (bit for bit as single lattices), and removing the closed
+    lattice afterwards only drops it from the binding's list."""
+    a, c = build(0, 620), build(2, 621)
+    ref = build(2, 621)
+    b = lbm.Batch(a.stream)
+    b.add(a, 100)
+    b.add(c, 100)
+    b.step(3)
+    a.close()
+    assert len(b) == 1
+    b.remove(a)
+    b.step(4)
+    ref.step(7)
+    assert np.array_equal(c.get_f(), ref.get_f())
+    b.close()
+    c.close()
+    ref.close()
+
 def test_batch_rejects_unsupported_members():
     q = 18
     lat = lbm.Lattice(q, 8, 8, 8, svec(q, 1.2), storage="f64")

@@ -149,6 +149,35 @@ def test_fp16dev_matches_oracle(q, pattern, setup, rounding):
     lat.close()
 
 
+
+@pytest.mark.parametrize("q", (14, 18))
+def test_fp16dev_with_background_pressure_matches_oracle(q):
+    """FP16 deviations are stored from the rest equilibrium 3 w_a p0 of the
+    reference pressure p0 (one base per weight class).  With p0 = 0.3 every
+    population carries a common part of 0.05-0.1 that is never rounded: the
+    lattice starts at f_eq(p0, 0) exactly, and after steps from a random
+    state its error against the oracle is a few FP16 roundings of the
+    deviation f - 3 w p0, not of f."""
+    dims = DIMS[0]
+    faces, wall_u, F0, FA, FT = SETUPS["cavity_lid"]
+    s = rates(q)
+    p0 = 0.3
+    kw = dict(faces=FACESETS[faces], wall_u=wall_u, F0=F0, FA=FA, FT=FT)
+    lat = lbm.Lattice(q, *dims, s, storage="f16dev", pattern="aa", p0=p0, **kw)
+    pr = R.problem(q, *dims, s, **kw)
+    rest = R.init_eq(pr, 0, p0=p0)
+    assert np.max(np.abs(lat.get_f() - rest)) <= 1e-7 * np.max(np.abs(rest))
+    _, w, _, _, _, _ = R.lattice(q)
+    base = (3.0 * w * p0).reshape(q, 1, 1, 1)
+    lat.set_f(base + inputs.random_populations(q, *dims, seed=14))
+    f0 = lat.get_f()
+    k = 4
+    lat.step(k)
+    ref = R.run(pr, f0, 0, k)
+    err = np.linalg.norm(lat.get_f() - ref) / np.linalg.norm(ref - base)
+    assert err <= 2.0 * np.sqrt(k) * 2.0 ** -10, err
+    lat.close()
+
 def test_fp16_stochastic_rounding_is_unbiased():
     """Zero rates in a periodic box only move values, and a body force adds
     a Guo source of ~3e-7 per population and step -- far below half an FP16
