@@ -412,9 +412,19 @@ __device__ __forceinline__ void node_step_any(const LatticeArgs<typename Codec<S
     node_step<Q, ST, MODE, FORCED, true, BGK>(A, x, y, z);
 }
 
+// Work item of this workgroup in XCD-aware order.  Workgroups are
+// dispatched to the 8 XCDs in turn (w to XCD w % 8); this hands XCD k the
+// k-th contiguous range of [0, gridDim.x), so neighbouring rows, whose lines
+// the odd AA step shares, stay in one L2.  A bijection on [0, gridDim.x):
+// the first gridDim.x % 8 XCDs take one item more.
+__device__ __forceinline__ unsigned xcd_block() {
+  const unsigned G = gridDim.x, q8 = G >> 3, r8 = G & 7u, xc = blockIdx.x & 7u, i = blockIdx.x >> 3;
+  return xc < r8 ? xc * (q8 + 1u) + i : r8 * (q8 + 1u) + (xc - r8) * q8 + i;
+}
+
 template <int Q, int ST, int MODE, bool FORCED, bool BGK = false>
 __global__ __launch_bounds__(256) void k_step(LatticeArgs<typename Codec<ST>::C> A) {
-  const unsigned b = blockIdx.x;
+  const unsigned b = A.xcd_order ? xcd_block() : blockIdx.x;
   const unsigned r = fast_div(b, A.fd_tiles_x);
   const int bx = (int)(b - r * (unsigned)A.tiles_x);
   const unsigned zz = fast_div(r, A.fd_tiles_y);
@@ -1116,8 +1126,9 @@ __device__ __forceinline__ void batch_tile(const BatchMember& m, const float* __
 
 template <int Q, int ST, int MODE, bool FORCED>
 __global__ __launch_bounds__(256) void k_batch_grp(const BatchMember* __restrict__ ms, int nm,
-                                                   const float* __restrict__ ftab, int substep) {
-  const unsigned tile = blockIdx.x;
+                                                   const float* __restrict__ ftab, int substep,
+                                                   int xcd_order) {
+  const unsigned tile = xcd_order ? xcd_block() : blockIdx.x;
   const BatchMember& m = ms[find_member(ms, nm, tile)];
   const int own = substep - m.skip;  // this member's own step within the call
   if (own < 0 || own >= m.steps) return;
@@ -1132,8 +1143,8 @@ template <int Q, int ST, int MODE, bool FORCED>
 __global__ __launch_bounds__(256) void k_batch_chunk(const BatchMember* __restrict__ ms,
                                                      const BatchChunk* __restrict__ chunks,
                                                      const float* __restrict__ ftab,
-                                                     int substep) {
-  const BatchChunk ch = chunks[blockIdx.x];
+                                                     int substep, int xcd_order) {
+  const BatchChunk ch = chunks[xcd_order ? xcd_block() : blockIdx.x];
   const BatchMember& m = ms[ch.member];
   const int own = substep - m.skip;
   if (own < 0 || own >= m.steps) return;
@@ -1146,10 +1157,10 @@ template <int Q, int ST, int MODE, bool FORCED>
 static void batch_launch_k(const BatchLaunch& L, hipStream_t s) {
   if (L.chunks)
     hipLaunchKernelGGL((k_batch_chunk<Q, ST, MODE, FORCED>), dim3((unsigned)L.nblocks), dim3(256),
-                       0, s, L.members, L.chunks, L.ftab, L.substep);
+                       0, s, L.members, L.chunks, L.ftab, L.substep, L.xcd_order);
   else
     hipLaunchKernelGGL((k_batch_grp<Q, ST, MODE, FORCED>), dim3((unsigned)L.nblocks), dim3(256), 0,
-                       s, L.members, L.nmembers, L.ftab, L.substep);
+                       s, L.members, L.nmembers, L.ftab, L.substep, L.xcd_order);
 }
 
 template <int Q, int ST>

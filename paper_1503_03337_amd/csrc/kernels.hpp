@@ -43,6 +43,8 @@ template <typename C> struct LatticeArgs {
   int sym;                 // bit f set: face f (-x,+x,-y,+y,-z,+z) is a
                            // symmetry plane (specular reflection)
   int tx, ty, tiles_x, tiles_y;  // x-y tile of one workgroup
+  int xcd_order;           // 1: each XCD takes a contiguous range of tiles
+                           // (workgroup w runs on XCD w % 8); 0: tile = w
   C sN[18], hN[18];        // s_k/N_k, (1 - s_k/2)/N_k
   C bb[18][3];             // 6 w_a (c_a . u_w) for link a leaving through
                            // the x / y / z face it crosses
@@ -148,6 +150,7 @@ struct BatchLaunch {
   long long nblocks;
   const float* ftab;
   int substep;
+  int xcd_order;  // 1: XCD-aware workgroup order (as LatticeArgs::xcd_order)
 };
 hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const BatchLaunch& L,
                               hipStream_t stream);
