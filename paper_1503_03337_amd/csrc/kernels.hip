@@ -412,19 +412,33 @@ __device__ __forceinline__ void node_step_any(const LatticeArgs<typename Codec<S
     node_step<Q, ST, MODE, FORCED, true, BGK>(A, x, y, z);
 }
 
-// Work item of this workgroup in XCD-aware order.  Workgroups are
-// dispatched to the 8 XCDs in turn (w to XCD w % 8); this hands XCD k the
-// k-th contiguous range of [0, gridDim.x), so neighbouring rows, whose lines
-// the odd AA step shares, stay in one L2.  A bijection on [0, gridDim.x):
-// the first gridDim.x % 8 XCDs take one item more.
-__device__ __forceinline__ unsigned xcd_block() {
-  const unsigned G = gridDim.x, q8 = G >> 3, r8 = G & 7u, xc = blockIdx.x & 7u, i = blockIdx.x >> 3;
+// Work item of this workgroup in an XCD-aware order.  Workgroups are
+// dispatched to the 8 XCDs in turn (w to XCD w % 8).  xcd_contiguous hands
+// XCD k the k-th contiguous range of [0, gridDim.x) (the first
+// gridDim.x % 8 XCDs take one item more); xcd_block(c), c >= 2, hands the
+// XCDs chunks of 2^(c-1) consecutive items in turn (items past the last
+// whole round of 8 chunks keep w), and c = 1 is xcd_contiguous.  Each is a
+// bijection on [0, gridDim.x), so neighbouring rows, whose lines the odd AA
+// step shares, run in one L2 without changing what any item computes.  The
+// single-lattice step uses xcd_contiguous only: the chunked branch there
+// made the compiler spill scalar registers and cost 1.4 % at 128^3.
+__device__ __forceinline__ unsigned xcd_contiguous() {
+  const unsigned G = gridDim.x, q8 = G >> 3, r8 = G & 7u, xc = blockIdx.x & 7u,
+                 i = blockIdx.x >> 3;
   return xc < r8 ? xc * (q8 + 1u) + i : r8 * (q8 + 1u) + (xc - r8) * q8 + i;
+}
+
+__device__ __forceinline__ unsigned xcd_block(int order) {
+  if (order == 1) return xcd_contiguous();
+  const unsigned G = gridDim.x, w = blockIdx.x, xc = w & 7u, i = w >> 3;
+  const unsigned sh = (unsigned)order - 1u, whole = (G >> (sh + 3u)) << (sh + 3u);
+  if (w >= whole) return w;
+  return ((i >> sh) << (sh + 3u)) + (xc << sh) + (i & ((1u << sh) - 1u));
 }
 
 template <int Q, int ST, int MODE, bool FORCED, bool BGK = false>
 __global__ __launch_bounds__(256) void k_step(LatticeArgs<typename Codec<ST>::C> A) {
-  const unsigned b = A.xcd_order ? xcd_block() : blockIdx.x;
+  const unsigned b = A.xcd_order ? xcd_contiguous() : blockIdx.x;
   const unsigned r = fast_div(b, A.fd_tiles_x);
   const int bx = (int)(b - r * (unsigned)A.tiles_x);
   const unsigned zz = fast_div(r, A.fd_tiles_y);
@@ -1128,7 +1142,7 @@ template <int Q, int ST, int MODE, bool FORCED>
 __global__ __launch_bounds__(256) void k_batch_grp(const BatchMember* __restrict__ ms, int nm,
                                                    const float* __restrict__ ftab, int substep,
                                                    int xcd_order) {
-  const unsigned tile = xcd_order ? xcd_block() : blockIdx.x;
+  const unsigned tile = xcd_order ? xcd_block(xcd_order) : blockIdx.x;
   const BatchMember& m = ms[find_member(ms, nm, tile)];
   const int own = substep - m.skip;  // this member's own step within the call
   if (own < 0 || own >= m.steps) return;
@@ -1144,7 +1158,7 @@ __global__ __launch_bounds__(256) void k_batch_chunk(const BatchMember* __restri
                                                      const BatchChunk* __restrict__ chunks,
                                                      const float* __restrict__ ftab,
                                                      int substep, int xcd_order) {
-  const BatchChunk ch = chunks[xcd_order ? xcd_block() : blockIdx.x];
+  const BatchChunk ch = chunks[xcd_order ? xcd_block(xcd_order) : blockIdx.x];
   const BatchMember& m = ms[ch.member];
   const int own = substep - m.skip;
   if (own < 0 || own >= m.steps) return;

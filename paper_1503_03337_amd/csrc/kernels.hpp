@@ -43,8 +43,9 @@ template <typename C> struct LatticeArgs {
   int sym;                 // bit f set: face f (-x,+x,-y,+y,-z,+z) is a
                            // symmetry plane (specular reflection)
   int tx, ty, tiles_x, tiles_y;  // x-y tile of one workgroup
-  int xcd_order;           // 1: each XCD takes a contiguous range of tiles
-                           // (workgroup w runs on XCD w % 8); 0: tile = w
+  int xcd_order;           // tile order (workgroup w runs on XCD w % 8):
+                           // 0 tile = w; 1 a contiguous range of tiles per
+                           // XCD
   C sN[18], hN[18];        // s_k/N_k, (1 - s_k/2)/N_k
   C bb[18][3];             // 6 w_a (c_a . u_w) for link a leaving through
                            // the x / y / z face it crosses
@@ -150,7 +151,8 @@ struct BatchLaunch {
   long long nblocks;
   const float* ftab;
   int substep;
-  int xcd_order;  // 1: XCD-aware workgroup order (as LatticeArgs::xcd_order)
+  int xcd_order;  // workgroup order: 0 dispatch, 1 contiguous ranges per XCD,
+                  // c >= 2 chunks of 2^(c-1) workgroups per XCD in turn
 };
 hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const BatchLaunch& L,
                               hipStream_t stream);

@@ -208,19 +208,40 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
   } while (0)
 
-// Tile order of the single-lattice step: XCD-aware (contiguous ranges of
-// tiles per XCD) up to 384 MB of populations, in dispatch order beyond.
-// Measured on D3Q18 AA cavities against dispatch order: FP32 +3 % at 96 MB,
+// Workgroup order of the step kernels (a lattice, or all active members of
+// a batch): one contiguous range of tiles per XCD up to 384 MB of
+// populations (beyond: below).  The contiguous ranges, measured on
+// D3Q18 AA cavities against dispatch order: FP32 +3 % at 96 MB,
 // +1.3 % at 144 MB (128^3), +10-14 % at 172-241 MB, +1.5-3 % at 281-374 MB,
 // but -4.6 % at 486 MB and -5.5 % at 1.2 GB (256^3); FP16 deviations
 // +2-13 % at 72-308 MB; FP64 unchanged.
 #ifndef LBM_XCD_ORDER_MAX_BYTES
 #define LBM_XCD_ORDER_MAX_BYTES (384ull << 20)
 #endif
+// Beyond that size a single lattice keeps dispatch order (chunks of 4 rows
+// per XCD were +0.4-2.9 % from HBM but need code in the step kernel that
+// cost 1.4 % in the cache), and a batch hands out chunks of
+// LBM_XCD_CHUNK_BATCH workgroups (512 nodes each) per XCD in turn: the
+// 256-cavity batch (4.85 GB) +3.1 % at 64 (+0.4 % at 4, +2.7 % at 16).
+#ifndef LBM_XCD_CHUNK_BATCH
+#define LBM_XCD_CHUNK_BATCH 64
+#endif
+static_assert(LBM_XCD_CHUNK_BATCH == 0 || (LBM_XCD_CHUNK_BATCH & (LBM_XCD_CHUNK_BATCH - 1)) == 0,
+              "LBM_XCD_CHUNK_BATCH must be 0 or a power of two");
+// xcd_order of the batch kernels for chunks of K = 2^k workgroups: k + 1
+// (K <= 1: chunks of one are the dispatch order, 0).
+constexpr int chunk_order(unsigned K) {
+  int k = 0;
+  while ((1u << k) < K) ++k;
+  return K > 1 ? k + 1 : 0;
+}
 size_t step_bytes(const lbm_ctx& c) {
   return population_bytes(c.q, c.N, c.spec.storage) * (c.spec.pattern == LBM_AB ? 2 : 1);
 }
-bool xcd_order(const lbm_ctx& c) { return step_bytes(c) <= (size_t)LBM_XCD_ORDER_MAX_BYTES; }
+int order_for(size_t bytes, bool batch) {
+  if (bytes <= (size_t)LBM_XCD_ORDER_MAX_BYTES) return 1;
+  return batch ? chunk_order(LBM_XCD_CHUNK_BATCH) : 0;
+}
 
 template <typename C>
 void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
@@ -247,7 +268,7 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
     if (c.spec.face[f] == LBM_SYMMETRY) A.sym |= 1 << f;
   A.tx = c.tx;
   A.ty = c.ty;
-  A.xcd_order = xcd_order(c) ? 1 : 0;
+  A.xcd_order = order_for(step_bytes(c), false);
   A.tiles_x = (c.nx + c.tx - 1) / c.tx;
   A.tiles_y = (c.ny + c.ty - 1) / c.ty;
   A.fd_tiles_x = make_fastdiv((unsigned)A.tiles_x);
@@ -1158,7 +1179,7 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   // active members (the class launches of a step follow each other)
   size_t act_bytes = 0;
   for (int j = 0; j < nm; ++j) act_bytes += step_bytes(*b->members[act[j]].ctx);
-  const int xcd = act_bytes <= (size_t)LBM_XCD_ORDER_MAX_BYTES ? 1 : 0;
+  const int xcd = order_for(act_bytes, true);
   nmax = 0;
   for (int k = 0; k < NG; ++k) nmax = std::max(nmax, cls_steps[k]);
   for (long long s = 0; s < nmax; ++s)
