@@ -304,7 +304,9 @@ int lbm_batch_destroy(lbm_batch* b);
 /* ---- measurement helper -----------------------------------------------
  * Copy `bytes` (multiple of 16) from src to dst on the device with a plain
  * streaming kernel, `reps` times back to back; the achievable-bandwidth
- * reference against which the step kernels are read.  Queued on stream. */
+ * reference against which the step kernels are read.  Its workgroup order
+ * is the faster one measured for the bytes touched: dispatch order up to
+ * 384 MB, one contiguous range per XCD beyond.  Queued on stream. */
 int lbm_copy_probe(void* dst, const void* src, size_t bytes, int reps, void* stream);
 
 #ifdef __cplusplus

@@ -104,7 +104,7 @@ hipError_t launch_monitor(int q, int storage, int phase, const void* args, void*
 hipError_t launch_reduce_partials(const double* partial, int nblocks, double* out,
                                   hipStream_t stream);
 int monitor_blocks(long long nodes);
-hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, hipStream_t stream);
+hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, int xcd, hipStream_t stream);
 
 // ---- batched execution -------------------------------------------------
 // One member of a batch, as the batched kernel sees it (FP32 compute).

@@ -864,8 +864,12 @@ int lbm_destroy(lbm_ctx* c) {
 
 int lbm_copy_probe(void* dst, const void* src, size_t bytes, int reps, void* stream) {
   if (!dst || !src || bytes % 16 || reps < 0) return LBM_EINVAL;
+  // the faster workgroup order for the bytes touched (XCD-contiguous from HBM)
+  const size_t touched = dst == src ? bytes : 2 * bytes;
+  const int xcd = touched > (size_t)LBM_XCD_ORDER_MAX_BYTES ? 1 : 0;
   for (int i = 0; i < reps; ++i)
-    if (launch_copy_probe(dst, src, bytes, (hipStream_t)stream) != hipSuccess) return LBM_EDEVICE;
+    if (launch_copy_probe(dst, src, bytes, xcd, (hipStream_t)stream) != hipSuccess)
+      return LBM_EDEVICE;
   return LBM_OK;
 }
 

@@ -501,3 +501,22 @@ def test_zero_steps_change_nothing():
     assert lat.time == 0 and np.array_equal(lat.get_f(), f0)
     b.close()
     lat.close()
+
+
+@pytest.mark.parametrize("nbytes", (16 * 1000003, 16 * ((200 << 20) // 16 + 12345)))
+def test_copy_probe_copies_in_either_order(nbytes):
+    """The bandwidth reference is a real copy in both workgroup orders: a
+    ragged 16 MB buffer (dispatch order) and a ragged 200 MB one (400 MB
+    touched: one contiguous range per XCD) arrive intact, and a copy in
+    place leaves the buffer as it was."""
+    import torch
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda", generator=gen)
+    dst = torch.zeros_like(src)
+    ref = src.clone()
+    stream = torch.cuda.current_stream().cuda_stream
+    lbm.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, 2, stream)
+    lbm.copy_probe(src.data_ptr(), src.data_ptr(), nbytes, 1, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, ref)
+    assert torch.equal(src, ref)
