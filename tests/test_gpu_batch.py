@@ -336,3 +336,35 @@ def test_cavity_batch_256_full_size():
             assert np.linalg.norm(u - ur) <= 1e-5 * np.linalg.norm(ur), k
     for lat, _ in lats:
         lat.close()
+
+
+def test_batch_beyond_384mb_equals_single_lattices():
+    """A batch whose members hold more than 384 MB hands the XCDs chunks of
+    workgroups in turn (another order than a smaller batch or a single
+    lattice uses).  The order changes no result: a D3Q18 member of 18.5k
+    tiles (the chunked kernel) and a ragged D3Q14 member (one tile per
+    workgroup), 464 MB together, equal single lattices bit for bit after an
+    even and an odd step and one more."""
+    members = [(18, (168, 168, 168), {"+z": (0.05, 0.0, 0.0)}),
+               (14, (130, 131, 129), {"+z": (0.0, 0.04, 0.0)})]
+    lats, singles = [], []
+    for k, (q, dims, lid) in enumerate(members):
+        for group in (lats, singles):
+            lat = lbm.Lattice(q, *dims, rates(q, k), faces=("wall",) * 6, wall_u=lid,
+                              storage="f32", pattern="aa")
+            lat.set_f(inputs.random_populations(q, *dims, seed=640 + k))
+            group.append(lat)
+    total = sum(lbm.footprint_bytes(l.q, l.nx, l.ny, l.nz, storage="f32", pattern="aa")
+                for l in lats)
+    assert total > 384 << 20
+    b = lbm.Batch(lats[0].stream)
+    for lat in lats:
+        b.add(lat, 100)
+    b.step(2)
+    b.step(1)
+    for lat, single in zip(lats, singles):
+        single.step(3)
+        assert np.array_equal(lat.get_f(), single.get_f())
+    b.close()
+    for lat in lats + singles:
+        lat.close()
