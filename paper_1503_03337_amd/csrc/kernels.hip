@@ -420,8 +420,9 @@ __device__ __forceinline__ void node_step_any(const LatticeArgs<typename Codec<S
 // whole round of 8 chunks keep w), and c = 1 is xcd_contiguous.  Each is a
 // bijection on [0, gridDim.x), so neighbouring rows, whose lines the odd AA
 // step shares, run in one L2 without changing what any item computes.  The
-// single-lattice step uses xcd_contiguous only: the chunked branch there
-// made the compiler spill scalar registers and cost 1.4 % at 128^3.
+// single-lattice step does not call xcd_block: its general chunk branch made
+// the compiler spill scalar registers there and cost 1.4 % at 128^3.  It
+// uses xcd_contiguous, or chunks of 4 written as a bit permutation.
 __device__ __forceinline__ unsigned xcd_contiguous() {
   const unsigned G = gridDim.x, q8 = G >> 3, r8 = G & 7u, xc = blockIdx.x & 7u,
                  i = blockIdx.x >> 3;
@@ -438,7 +439,14 @@ __device__ __forceinline__ unsigned xcd_block(int order) {
 
 template <int Q, int ST, int MODE, bool FORCED, bool BGK = false>
 __global__ __launch_bounds__(256) void k_step(LatticeArgs<typename Codec<ST>::C> A) {
-  const unsigned b = A.xcd_order ? xcd_contiguous() : blockIdx.x;
+  unsigned b = blockIdx.x;
+  if (A.xcd_order == 1) {
+    b = xcd_contiguous();
+  } else if (A.xcd_order == 2 && b < (gridDim.x & ~31u)) {
+    // chunks of 4 tiles per XCD in turn (xcd_block(3)): within each run of
+    // 32 workgroups, a permutation of the low five bits
+    b = (b & ~31u) | ((b & 7u) << 2) | ((b >> 3) & 3u);
+  }
   const unsigned r = fast_div(b, A.fd_tiles_x);
   const int bx = (int)(b - r * (unsigned)A.tiles_x);
   const unsigned zz = fast_div(r, A.fd_tiles_y);

@@ -45,7 +45,7 @@ template <typename C> struct LatticeArgs {
   int tx, ty, tiles_x, tiles_y;  // x-y tile of one workgroup
   int xcd_order;           // tile order (workgroup w runs on XCD w % 8):
                            // 0 tile = w; 1 a contiguous range of tiles per
-                           // XCD
+                           // XCD; 2 chunks of 4 tiles per XCD in turn
   C sN[18], hN[18];        // s_k/N_k, (1 - s_k/2)/N_k
   C bb[18][3];             // 6 w_a (c_a . u_w) for link a leaving through
                            // the x / y / z face it crosses

@@ -218,9 +218,11 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
 #ifndef LBM_XCD_ORDER_MAX_BYTES
 #define LBM_XCD_ORDER_MAX_BYTES (384ull << 20)
 #endif
-// Beyond that size a single lattice keeps dispatch order (chunks of 4 rows
-// per XCD were +0.4-2.9 % from HBM but need code in the step kernel that
-// cost 1.4 % in the cache), and a batch hands out chunks of
+// Beyond that size a single lattice hands the XCDs chunks of 4 rows in turn
+// (xcd_order 2, a permutation of the low five bits of the workgroup index
+// in the step kernel; from HBM +0.4-2.9 % over dispatch order, measured with
+// a general chunk code that cost 1.4 % in the cache by spilling scalar
+// registers, which this one does not), and a batch hands out chunks of
 // LBM_XCD_CHUNK_BATCH workgroups (512 nodes each) per XCD in turn: the
 // 256-cavity batch (4.85 GB) +3.1 % at 64 (+0.4 % at 4, +2.7 % at 16).
 #ifndef LBM_XCD_CHUNK_BATCH
@@ -240,7 +242,7 @@ size_t step_bytes(const lbm_ctx& c) {
 }
 int order_for(size_t bytes, bool batch) {
   if (bytes <= (size_t)LBM_XCD_ORDER_MAX_BYTES) return 1;
-  return batch ? chunk_order(LBM_XCD_CHUNK_BATCH) : 0;
+  return batch ? chunk_order(LBM_XCD_CHUNK_BATCH) : 2;
 }
 
 template <typename C>
