@@ -368,3 +368,28 @@ def test_batch_beyond_384mb_equals_single_lattices():
     b.close()
     for lat in lats + singles:
         lat.close()
+
+
+def test_large_single_lattice_orders_agree():
+    """Beyond 384 MB a single lattice gives the XCDs chunks of 4 rows in turn
+    and a batch chunks of 64 workgroups: a 180^3 D3Q18 FP32 lattice (420 MB;
+    32,400 rows, so the last 16 workgroups keep their place) stepped alone
+    and as the only member of a batch gives the same populations bit for
+    bit, from random ones, after an even, an odd and another even step."""
+    q, n = 18, 180
+    pair = []
+    for _ in range(2):
+        lat = lbm.Lattice(q, n, n, n, rates(q, 1), faces=("wall",) * 6,
+                          wall_u={"+z": (0.05, 0.02, 0.0)}, storage="f32", pattern="aa")
+        lat.set_f(inputs.random_populations(q, n, n, n, seed=650))
+        pair.append(lat)
+    assert lbm.footprint_bytes(q, n, n, n, storage="f32", pattern="aa") > 384 << 20
+    alone, member = pair
+    alone.step(3)
+    b = lbm.Batch(member.stream)
+    b.add(member, 3)
+    b.step(3)
+    assert np.array_equal(alone.get_f(), member.get_f())
+    b.close()
+    alone.close()
+    member.close()
