@@ -11,8 +11,14 @@
  * product path never calls it, and it shares no code, table or header with
  * the HIP library.
  *
+ * The closing paragraph of Appendix B notes that the same construction of
+ * the (q-1) x (q-1) transform gives a 26-velocity model (iD3Q26) as well,
+ * without spelling it out; it is built here by that construction (see
+ * "the 26-velocity model" below).
+ *
  * What is followed, and where:
- *   velocity sets ........ Sec. 3 (iD3Q14) and Appendix B (iD3Q18)
+ *   velocity sets ........ Sec. 3 (iD3Q14) and Appendix B (iD3Q18); the
+ *                          26 non-rest D3Q27 velocities for iD3Q26
  *   weights .............. Eq. (omega) for the D3Q19 lattice (Appendix B);
  *                          for the 14-velocity model the D3Q15 weights
  *                          2/9, 1/9, 1/72 (the printed Eq. (omega) lists the
@@ -62,7 +68,7 @@
 #include <omp.h>
 #endif
 
-#define QMAX 18
+#define QMAX 26
 
 /* ---- lattices (Sec. 3 for q = 14, Appendix B for q = 18) ------------- */
 static const int VEL14[14][3] = {
@@ -113,6 +119,74 @@ static const int TMAT18[18][18] = {
     {0, 0, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, 1, -1, 1, -1},
     {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, -1, -1, -1, -1, 1, 1}};
 
+/* ---- the 26-velocity model (closing paragraph of Appendix B) ------------
+ * Velocities: the six axis ones and the twelve edge ones in the order of
+ * Appendix B, then the eight corners in the order of Sec. 3.  Weights: those
+ * of the D3Q27 lattice the model is cut from, 2/27 (axis), 1/54 (edge),
+ * 1/216 (corner), rest weight 8/27 (the role the D3Q15 and D3Q19 weights
+ * play for 14 and 18 velocities).
+ *
+ * Transform: Sec. 3 builds T by Gram-Schmidt orthogonalisation of monomial
+ * rows c_x^m c_y^n c_z^l chosen per tensor order (Eq. (transformation_Mbar),
+ * Eq. (m)).  On these 26 velocities the monomials fall into the classes
+ *   scalars ......... 1, |c|^2, |c|^4                    (P, e, eps)
+ *   vectors ......... c_x, |c|^2 c_x, |c|^4 c_x, y, z    (j, q, h)
+ *   2nd order ....... 3c_x^2, 3c_x^2|c|^2, c_y^2 - c_z^2, (c_y^2 - c_z^2)|c|^2,
+ *                     c_x c_y, c_y c_z, c_x c_z and the same times |c|^2
+ *   3rd order ....... (c_y^2 - c_z^2)c_x, (c_z^2 - c_x^2)c_y,
+ *                     (c_x^2 - c_y^2)c_z, c_x c_y c_z
+ * (26 independent rows; the rest population, and with it one scalar, is
+ * dropped as for 14 and 18 velocities).  Orthogonalised in the order of
+ * the moment vector below and scaled to the smallest integers, the rows
+ * are the polynomials of t26_row.  Moments, in this order:
+ *   (P, e, eps, j_x, q_x, h_x, j_y, q_y, h_y, j_z, q_z, h_z, 3p_xx, 3pi_xx,
+ *    p_ww, pi_ww, p_xy, p_yz, p_xz, pi_xy, pi_yz, pi_xz, t_x, t_y, t_z, t_xyz).
+ * Their equilibria and forcing moments are not printed anywhere: they are
+ * computed from their definitions, m_eq = T f_eq (Sec. 3, with Eq. (edf))
+ * and m_F = T (the Guo source written in velocity space). */
+static const int VEL26[26][3] = {
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},   {0, 0, -1},  {1, 1, 0},
+    {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0}, {1, 0, 1}, {-1, 0, 1},  {1, 0, -1},  {-1, 0, -1},
+    {0, 1, 1},  {0, -1, 1}, {0, 1, -1},  {0, -1, -1}, {1, 1, 1}, {-1, 1, 1}, {1, -1, 1},
+    {-1, -1, 1}, {1, 1, -1}, {-1, 1, -1}, {1, -1, -1}, {-1, -1, -1}};
+
+/* Row k of the 26 x 26 transform at velocity c (k2 = |c|^2). */
+static int t26_row(int k, const int* c) {
+  const int x = c[0], y = c[1], z = c[2], k2 = x * x + y * y + z * z;
+  const int q = 3 * k2 - 7;                          /* energy flux  */
+  const int h = (9 * k2 * k2 - 39 * k2 + 38) / 2;    /* second flux  */
+  const int r = 3 * k2 - 5;                          /* pi_xx, pi_ww */
+  const int s = 3 * k2 - 8;                          /* pi_xy ...    */
+  switch (k) {
+    case 0: return 1;
+    case 1: return 13 * k2 - 27;
+    case 2: return (15 * k2 * k2 - 61 * k2 + 54) / 2;
+    case 3: return x;
+    case 4: return q * x;
+    case 5: return h * x;
+    case 6: return y;
+    case 7: return q * y;
+    case 8: return h * y;
+    case 9: return z;
+    case 10: return q * z;
+    case 11: return h * z;
+    case 12: return 3 * x * x - k2;
+    case 13: return r * (3 * x * x - k2);
+    case 14: return y * y - z * z;
+    case 15: return r * (y * y - z * z);
+    case 16: return x * y;
+    case 17: return y * z;
+    case 18: return x * z;
+    case 19: return s * x * y;
+    case 20: return s * y * z;
+    case 21: return s * x * z;
+    case 22: return (y * y - z * z) * x;
+    case 23: return (z * z - x * x) * y;
+    case 24: return (x * x - y * y) * z;
+    default: return x * y * z;
+  }
+}
+
 /* The lattice in use, with the derived quantities the step needs. */
 typedef struct {
   int q;
@@ -126,22 +200,26 @@ typedef struct {
 
 static int make_lattice(int q, lattice* L) {
   int a, b, k, d;
-  if (q != 14 && q != 18) return -1;
+  if (q != 14 && q != 18 && q != 26) return -1;
   memset(L, 0, sizeof(*L));
   L->q = q;
   for (a = 0; a < q; ++a) {
     int len2 = 0;
     for (d = 0; d < 3; ++d) {
-      L->c[a][d] = (q == 14) ? VEL14[a][d] : VEL18[a][d];
+      L->c[a][d] = (q == 14) ? VEL14[a][d] : (q == 18) ? VEL18[a][d] : VEL26[a][d];
       len2 += L->c[a][d] * L->c[a][d];
     }
     if (q == 14)
       L->w[a] = (len2 == 1) ? 1.0 / 9.0 : 1.0 / 72.0;
-    else
+    else if (q == 18)
       L->w[a] = (len2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
-    for (b = 0; b < q; ++b) L->T[a][b] = (q == 14) ? TMAT14[a][b] : TMAT18[a][b];
+    else
+      L->w[a] = (len2 == 1) ? 2.0 / 27.0 : (len2 == 2) ? 1.0 / 54.0 : 1.0 / 216.0;
   }
-  L->w0 = (q == 14) ? 2.0 / 9.0 : 1.0 / 3.0;
+  for (k = 0; k < q; ++k)
+    for (b = 0; b < q; ++b)
+      L->T[k][b] = (q == 14) ? TMAT14[k][b] : (q == 18) ? TMAT18[k][b] : t26_row(k, L->c[b]);
+  L->w0 = (q == 14) ? 2.0 / 9.0 : (q == 18) ? 1.0 / 3.0 : 8.0 / 27.0;
   for (a = 0; a < q; ++a) {
     L->opp[a] = -1;
     for (b = 0; b < q; ++b)
@@ -286,6 +364,45 @@ static void mforce_node(int q, const double u[3], const double F[3], double* mF)
   }
 }
 
+/* The Guo source in velocity space, w_a [3 c.F + 9 (c.u)(c.F) - 3 u.F]:
+ * T applied to it gives the forcing moments m_F = (d m_eq / d u) . F. */
+static void guo_source(const lattice* L, const double u[3], const double F[3], double* src) {
+  int a;
+  double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  for (a = 0; a < L->q; ++a) {
+    double cu = L->c[a][0] * u[0] + L->c[a][1] * u[1] + L->c[a][2] * u[2];
+    double cF = L->c[a][0] * F[0] + L->c[a][1] * F[1] + L->c[a][2] * F[2];
+    src[a] = L->w[a] * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+  }
+}
+
+/* m = T v for a vector v over the velocities. */
+static void transform(const lattice* L, const double* v, double* m) {
+  int a, k;
+  for (k = 0; k < L->q; ++k) {
+    double acc = 0.0;
+    for (a = 0; a < L->q; ++a) acc += L->T[k][a] * v[a];
+    m[k] = acc;
+  }
+}
+
+/* Moment equilibria and forcing moments of the lattice in use: the printed
+ * closed forms for 14 and 18 velocities; for 26 velocities (none printed)
+ * their definitions m_eq = T f_eq and m_F = T (Guo source). */
+static void moment_eq_force(const lattice* L, double p, const double u[3], const double F[3],
+                            double* meq, double* mF) {
+  if (L->q == 26) {
+    double fe[QMAX], src[QMAX];
+    feq_node(L, p, u, fe);
+    guo_source(L, u, F, src);
+    transform(L, fe, meq);
+    transform(L, src, mF);
+  } else {
+    meq_node(L->q, p, u, meq);
+    mforce_node(L->q, u, F, mF);
+  }
+}
+
 /* One collision, Eq. (mrteqvT):
  *   m = T f;  D_k = s_k (m_k - meq_k) - (1 - s_k/2) mF_k;
  *   f*_a = f_a - sum_k T_ka D_k / N_k. */
@@ -294,13 +411,8 @@ static void collide_node(const lattice* L, const double* s, const double* f,
   int a, k, q = L->q;
   double p, u[3], m[QMAX], meq[QMAX], mF[QMAX], D[QMAX];
   macro_node(L, f, F, &p, u);
-  for (k = 0; k < q; ++k) {
-    double acc = 0.0;
-    for (a = 0; a < q; ++a) acc += L->T[k][a] * f[a];
-    m[k] = acc;
-  }
-  meq_node(q, p, u, meq);
-  mforce_node(q, u, F, mF);
+  transform(L, f, m);
+  moment_eq_force(L, p, u, F, meq, mF);
   for (k = 0; k < q; ++k)
     D[k] = s[k] * (m[k] - meq[k]) - (1.0 - 0.5 * s[k]) * mF[k];
   for (a = 0; a < q; ++a) {
@@ -571,14 +683,18 @@ int orc_macro_node(int q, const double* f, const double* F, double* p, double* u
 }
 
 int orc_meq(int q, double p, const double* u, double* meq) {
-  if (q != 14 && q != 18) return -1;
-  meq_node(q, p, u, meq);
+  lattice L;
+  double F[3] = {0.0, 0.0, 0.0}, mF[QMAX];
+  if (make_lattice(q, &L)) return -1;
+  moment_eq_force(&L, p, u, F, meq, mF);
   return 0;
 }
 
 int orc_mforce(int q, const double* u, const double* F, double* mF) {
-  if (q != 14 && q != 18) return -1;
-  mforce_node(q, u, F, mF);
+  lattice L;
+  double meq[QMAX];
+  if (make_lattice(q, &L)) return -1;
+  moment_eq_force(&L, 0.0, u, F, meq, mF);
   return 0;
 }
 

@@ -16,7 +16,7 @@ FACES = ("-x", "+x", "-y", "+y", "-z", "+z")
 class Problem(C.Structure):
     _fields_ = [
         ("q", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
-        ("s", C.c_double * 18),
+        ("s", C.c_double * 26),
         ("face", C.c_int * 6),
         ("wall_u", (C.c_double * 3) * 6),
         ("F0", C.c_double * 3), ("FA", C.c_double * 3),
@@ -98,9 +98,9 @@ def mforce(q, u, F):
 
 def collide(q, s, f, F=(0.0, 0.0, 0.0)):
     out = np.zeros(q)
-    s18 = np.zeros(18)
-    s18[:q] = s
-    _chk(lib().orc_collide(q, s18, np.ascontiguousarray(f, np.float64),
+    s26 = np.zeros(26)
+    s26[:q] = s
+    _chk(lib().orc_collide(q, s26, np.ascontiguousarray(f, np.float64),
                            np.asarray(F, np.float64), out), "collide")
     return out
 

@@ -78,6 +78,55 @@ def test_pulsatile_series_properties():
         assert abs(A.duct_pulsatile(s * a, b, 0.3, a, b, g, nu, om, 3000)) < 1e-3 * g / om
 
 
+def test_gre_u_on_fields_with_known_error():
+    """Eq. (ed) on constructed fields whose error is known exactly, so that a
+    missing square root (e^2 for e), a dropped cross-flow component, a sum
+    replaced by a mean, or a normalisation by the numerical field instead of
+    the analytic one each fails one case."""
+    rng = np.random.default_rng(3)
+    ua = np.zeros((3, 5, 6, 7))
+    ua[0] = rng.uniform(0.1, 1.0, (5, 6, 7))  # streamwise analytic field
+    # the exact field has no error
+    assert A.gre_u(ua, ua) == 0.0
+    # a uniform relative error e on every node and component gives e itself
+    for e in (1e-3, 0.05, 0.3):
+        assert abs(A.gre_u((1.0 + e) * ua, ua) - e) < 1e-14
+        assert abs(A.gre_u((1.0 - e) * ua, ua) - e) < 1e-14
+    # cross-flow alone: |(v, w)| = 0.5 |u_a| pointwise gives 0.5
+    un = ua.copy()
+    un[1] = 0.3 * ua[0]
+    un[2] = -0.4 * ua[0]
+    assert abs(A.gre_u(un, ua) - 0.5) < 1e-14
+    # one node off by d in a uniform unit field of n nodes: |d| / sqrt(n)
+    n = 5 * 6 * 7
+    uu = np.zeros((3, 5, 6, 7))
+    uu[0] = 1.0
+    un = uu.copy()
+    un[2, 1, 2, 3] = 0.02
+    assert abs(A.gre_u(un, uu) - 0.02 / np.sqrt(n)) < 1e-16
+    un = uu.copy()
+    un[0, 4, 5, 6] += 0.6
+    assert abs(A.gre_u(un, uu) - 0.6 / np.sqrt(n)) < 1e-15
+
+
+def test_served_duct_series_equals_the_oracle_series():
+    """The product's copy of the steady duct series (used to report the
+    accuracy of served duct solves) equals the oracle's Sec. 4.1 series on
+    the nodes of lattices with half-way walls (the points the served ducts
+    are compared at; on the walls themselves both truncate a series that
+    converges like 1/i^3) for several sizes, aspect ratios and viscosities."""
+    from paper_1503_03337_amd import duct_series
+    for ny, nz, g, nu in ((32, 32, 2.6e-4, 0.1), (10, 6, 1.0, 0.3), (160, 160, 3.0e-6, 1.3),
+                          (17, 41, 0.01, 0.05)):
+        a, b = ny / 2.0, nz / 2.0
+        y = A.node_coords(ny)
+        z = A.node_coords(nz)
+        Y, Z = np.meshgrid(y, z, indexing="xy")
+        got = duct_series.velocity(Y, Z, a, b, g, nu)
+        ref = A.duct_steady(Y, Z, a, b, g, nu)
+        assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref)), (ny, nz, g, nu)
+
+
 def test_paper_table_slopes():
     """The slopes quoted in Sec. 4.1 / 4.2 follow from Tables 1 and 2 by a
     least-squares fit of -ln GRE against -ln dx (second order)."""
@@ -92,7 +141,7 @@ def test_paper_table_slopes():
 
 # ---- the oracle against exact and analytic flows -------------------------
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_couette_is_exact(q):
     """Plane Couette flow between a resting wall and a moving lid: half-way
     bounce-back with the moving-wall term gives the exact linear profile."""
@@ -106,7 +155,7 @@ def test_couette_is_exact(q):
         assert np.max(np.abs(u[1:])) < 1e-15
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_force_driven_channel_exact_in_linear_limit(q):
     """Plane Poiseuille flow with a body force and half-way walls: with
     (1/s_nu - 1/2)(1/s_q - 1/2) = 3/16 (and s_t = s_q) the parabola is
@@ -133,10 +182,10 @@ def _trt_rates(q, nu, lam=3.0 / 16.0):
     (1/s_nu - 1/2)(1/s_o - 1/2) = lam: the MRT step reduces to two rates."""
     sn = s_nu_of(nu)
     so = 1.0 / (lam / (1.0 / sn - 0.5) + 0.5)
-    return svec(q, sn, s_q=so, s_t=so, s_e=sn, s_pi=sn)
+    return svec(q, sn, s_q=so, s_t=so, s_e=sn, s_pi=sn, s_eps=sn)
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_forced_duct_depends_on_lambda_only(q):
     """Steady forced flow through a square duct with half-way walls: with two
     rates tied by a fixed lam, the steady solution of the linear problem
@@ -172,7 +221,7 @@ def _duct_gre(q, n, nu, steps, nx=1, umax=0.05):
     return A.gre_u(u, ua)
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_steady_duct_second_order(q):
     errs = [_duct_gre(q, n, 0.1, st) for n, st in ((8, 1000), (16, 3000), (32, 9000))]
     slopes = np.diff(-np.log(errs)) / np.log(2.0)
@@ -211,7 +260,7 @@ def _pulsatile_gre(q, n, eta, period, periods=3):
     return np.array(errs[-4:])
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_pulsatile_second_order(q):
     """Sec. 4.2 with diffusive scaling (period ~ n^2, fixed Womersley
     number 5): GRE_u at T/4, T/2, 3T/4, T falls at second order."""
@@ -224,7 +273,7 @@ def test_pulsatile_second_order(q):
     assert np.max(e32) < 0.03
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_shear_wave_viscosity(q):
     """A small shear wave u_x = A sin(k z) in a periodic box decays at the
     rate nu k^2 with nu = (1/s_nu - 1/2)/3 (Eq. (vis)), up to O(k^2)."""

@@ -60,7 +60,7 @@ def pull_permutation(q, dims, faces, f):
     return out
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 @pytest.mark.parametrize("kind", sorted(FACESETS))
 def test_zero_rates_step_is_bit_exact_permutation(q, kind):
     dims = (5, 4, 3)
@@ -97,9 +97,9 @@ def exact_step(q, dims, faces, wall_u, s, F, f):
     Gauss-Jordan T^-1, f_eq from Eq. (edf), src the Guo source, u = sum c f +
     F/2, p from Eq. (hgl); then pull streaming with half-way bounce-back and
     the moving-wall term -6 w_a (c_a . u_w) of the outgoing link."""
-    from helpers import read_matrix
+    from helpers import T_matrix
     c = velocities(q)
-    T = [[Fr(int(v)) for v in r] for r in read_matrix("T%d_printed.txt" % q)]
+    T = [[Fr(int(v)) for v in r] for r in T_matrix(q)]
     Ti = _inverse(T)
     w0, w = weights_d3q15_d3q19(q)
     opp = [int(np.nonzero((c == -c[a]).all(axis=1))[0][0]) for a in range(q)]
@@ -152,7 +152,7 @@ def exact_step(q, dims, faces, wall_u, s, F, f):
     return out
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 @pytest.mark.parametrize("kind", ["cavity", "duct"])
 def test_bruteforce_4cube_exact(q, kind):
     """Two steps on a 4^3 lattice: oracle (FP64) against the exact-rational
@@ -181,7 +181,7 @@ def test_bruteforce_4cube_exact(q, kind):
         assert np.max(np.abs(got - exf)) <= 2e-15 * np.max(np.abs(exf))
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_uniform_equilibrium_is_fixed_point(q):
     pr = R.problem(q, 6, 5, 4, svec(q, 1.3), faces=FACESETS["periodic"])
     f = R.init_eq(pr, 0, p0=0.01, u0=(0.03, -0.02, 0.01))
@@ -189,7 +189,7 @@ def test_uniform_equilibrium_is_fixed_point(q):
     assert np.max(np.abs(g - f)) < 1e-16
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_mass_conserved_with_tangential_lid(q):
     """With walls and a tangential lid, sum of P = sum f is invariant
     (collision conserves P; a tangential wall adds +-pairs that cancel)."""
@@ -202,7 +202,7 @@ def test_mass_conserved_with_tangential_lid(q):
     assert abs(g.sum() - m0) <= 1e-13 * np.abs(f).sum()
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_momentum_grows_by_NF_per_step(q):
     """Periodic box with a body force: total j grows by exactly N F a step."""
     c = velocities(q).astype(float)
@@ -216,7 +216,7 @@ def test_momentum_grows_by_NF_per_step(q):
     assert np.max(np.abs(j1 - j0 - 7 * 60 * F)) < 1e-14 * np.abs(f).sum()
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_symmetry_plane_reproduces_full_channel(q):
     """Sec. 4.3 imposes Eq. (z05symmetry) on a mid-plane to compute half the
     cavity.  A force-driven channel between walls at both z ends must equal
@@ -237,7 +237,7 @@ def test_symmetry_plane_reproduces_full_channel(q):
     assert np.max(np.abs(uf[2] + uf[2, ::-1])) <= 1e-12 * np.max(np.abs(uf))
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 def test_symmetry_plane_reproduces_full_cavity(q):
     """Lid on +y moving along x: the cavity is mirror-symmetric in z, so its
     lower half equals the half cavity with a symmetry plane on +z, at every
