@@ -54,7 +54,15 @@ extern "C" {
 typedef struct lbm_ctx lbm_ctx;
 typedef struct lbm_batch lbm_batch;
 
-typedef enum { LBM_D3Q14 = 14, LBM_D3Q18 = 18 } lbm_model;
+/* LBM_D3Q26: the 26-velocity model the closing paragraph of Appendix B says
+ * the same construction gives (not spelled out in the paper; built here by
+ * Sec. 3's Gram-Schmidt of monomial rows): the 18 velocities above, then
+ * the 8 corners in the order of the 14-velocity model; D3Q27 weights 2/27,
+ * 1/54, 1/216 (rest weight 8/27); 26 moments (P, e, eps, j_x, q_x, h_x,
+ * j_y, q_y, h_y, j_z, q_z, h_z, 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz,
+ * p_xz, pi_xy, pi_yz, pi_xz, t_x, t_y, t_z, t_xyz), and s_vec in that order;
+ * p = 9/19 (P - 4/9 |u|^2) (Eq. (hgl) with w0 = 8/27). */
+typedef enum { LBM_D3Q14 = 14, LBM_D3Q18 = 18, LBM_D3Q26 = 26 } lbm_model;
 
 /* Population storage.  Arithmetic is FP64 for LBM_F64 and FP32 otherwise.
  * LBM_F16DEV stores h_a = fp16((f_a - 3 w_a p0) 2^s): the deviation from the
@@ -199,8 +207,27 @@ int lbm_create(lbm_ctx** out, int model, int nx, int ny, int nz,
  * captured) and launched on the context stream.  A
  * graph never spans a monitor step.  Results are bit-identical either way.
  * The first such call on a context captures (and keeps, until lbm_destroy)
- * up to two graphs, one per AA parity or A/B buffer order. */
+ * up to two graphs, one per AA parity or A/B buffer order.
+ *
+ * Failure: with spec.monitor_every = K > 0 the FP64 monitor runs every K
+ * steps (queued like the steps).  Its second pass keeps a flag on the
+ * device that stays set once any run has seen a non-finite mass or sum |u|
+ * (or, with an earlier snapshot of the state, a non-finite change of u), and
+ * copies it to host memory with its sums.  lbm_step reads that copy without
+ * waiting, at its start and before each monitor run it queues; once a run
+ * that has completed reports a non-finite value, lbm_step returns
+ * LBM_ENONFINITE at once (queuing nothing more) and keeps doing so until
+ * lbm_set_f or lbm_init_fields gives the context a new state.  A diverging
+ * lattice is therefore stopped at most a few monitor intervals after it
+ * turned non-finite, however long the caller keeps stepping it.  In a batch
+ * (lbm_batch_step) nothing is checked: use lbm_batch_monitor and lbm_poll. */
 int lbm_step(lbm_ctx* ctx, long long n);
+
+/* Non-blocking health check: LBM_ENONFINITE if a completed monitor run (of
+ * lbm_step, lbm_monitor or lbm_batch_monitor) has seen a non-finite value
+ * since the state was last set, LBM_OK otherwise (also while the last run
+ * is still in flight).  Never waits for the device. */
+int lbm_poll(lbm_ctx* ctx);
 
 /* Pressure p[N] and velocity u[3][N] (host, FP64) at the current time level
  * t, with u = sum c f + F(t)/2 (Eq. (hgl)).  Either pointer may be NULL.
@@ -217,9 +244,18 @@ int lbm_macros_device(lbm_ctx* ctx, double* p_dev, double* u_dev);
  * sum|u| = 0 or when the monitor had no earlier snapshot of the current state
  * (its first run, or the first after lbm_set_f, lbm_init_fields or
  * lbm_set_time).  LBM_ENONFINITE if the monitor saw a non-finite value in u,
- * the mass or (with an earlier snapshot) the change of u.  Synchronises the
- * stream. */
+ * the mass or (with an earlier snapshot) the change of u.  Waits for the
+ * last monitor run to complete (not for work queued after it). */
 int lbm_residual(lbm_ctx* ctx, double* r);
+
+/* The same change of u in the norm of the paper's steady-state criteria
+ * themselves (Eq. (sc) for L = 1, Eq. (cr) for L = T, Eq. (cavity_creterion)
+ * for L = 1000), not divided by the lag:
+ *   R_L = sum_n sum_k |u_k(n,t) - u_k(n,t-L)| / sum_n sum_k |u_k(n,t)|,
+ * and the lag L in *lag (may be NULL; 0 when the monitor had no earlier
+ * snapshot, R_L = +inf then).  lbm_residual returns R_L / L.  Status as for
+ * lbm_residual. */
+int lbm_residual_change(lbm_ctx* ctx, double* r, long long* lag);
 
 /* Mass M = sum_n P(n) = sum_n sum_a f_a(n) (FP64) from the last monitor run;
  * runs the monitor first if it has never run. */

@@ -1,4 +1,4 @@
-// kernels.hip -- device code of the D3Q14 / D3Q18 incompressible MRT
+// kernels.hip -- device code of the D3Q14 / D3Q18 / D3Q26 incompressible MRT
 // lattice Boltzmann library for gfx950 (arXiv 1503.03337).
 //
 // Data layout: structure of arrays, population a of node n at
@@ -113,10 +113,6 @@ template <> struct Codec<ST_F16> {
   }
 };
 
-// Weight class of population a in both models: 0 for the six axis
-// velocities, 1 for the others (the FP16 base depends on nothing else).
-__host__ __device__ constexpr int wclass(int a) { return a < 6 ? 0 : 1; }
-
 // Counter-based random words for the FP16 dither: one hash of (node, time
 // level) per node, then a Weyl sequence over the populations (marginally
 // uniform top bits at one add each).  Deterministic, so a lattice gives the
@@ -137,20 +133,21 @@ __device__ __forceinline__ unsigned pop_bits(unsigned h, int a) {
 // Encode a post-collision value: FP16 stochastically (SR) or to nearest,
 // the other storages plainly.  SR is a template argument so that a kernel
 // picks the rounding mode once per node, not once per population.
-template <int ST, bool SR>
+template <int Q, int ST, bool SR>
 __device__ __forceinline__ typename Codec<ST>::S enc_step(const LatticeArgs<typename Codec<ST>::C>& A,
                                                           typename Codec<ST>::C v, int slot,
                                                           unsigned h, int a) {
-  const typename Codec<ST>::C bs = A.base_s[wclass(slot)];
+  const typename Codec<ST>::C bs = A.base_s[wclass<Q>(slot)];
   if constexpr (ST == ST_F16 && SR) return Codec<ST>::enc_sr(v, bs, A.scale, pop_bits(h, a));
   return Codec<ST>::enc(v, bs, A.scale);
 }
 // The same with the mode read per value (code off the per-node hot path).
-template <int ST>
+template <int Q, int ST>
 __device__ __forceinline__ typename Codec<ST>::S enc_any(const LatticeArgs<typename Codec<ST>::C>& A,
                                                          typename Codec<ST>::C v, int slot,
                                                          unsigned h, int a) {
-  return A.f16_sr ? enc_step<ST, true>(A, v, slot, h, a) : enc_step<ST, false>(A, v, slot, h, a);
+  return A.f16_sr ? enc_step<Q, ST, true>(A, v, slot, h, a)
+                  : enc_step<Q, ST, false>(A, v, slot, h, a);
 }
 
 // ---- neighbour offsets -----------------------------------------------------
@@ -293,7 +290,7 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
   if (PHASE == 0) {
 #pragma unroll
     for (int a = 0; a < Q; ++a)
-      f[a] = CD::dec(pop_load<NT>((const S*)(p0 + A.pofs[a])), A.base[wclass(a)], A.inv_scale);
+      f[a] = CD::dec(pop_load<NT>((const S*)(p0 + A.pofs[a])), A.base[wclass<Q>(a)], A.inv_scale);
   } else {
     const Nbr b = make_nbr<GEN>(A, x, y, z);
     // x - c_a: direction k = (-cx > 0) of the link taken from this node
@@ -309,7 +306,7 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
       const char* nb = link_ptr<S, GEN>(A, b, p0, px, -L::cx[a], -L::cy[a], -L::cz[a], off,
                                         slot, o);
       const char* p = wall ? p0 + A.pofs[a] : nb;
-      f[a] = CD::dec(pop_load<NT>((const S*)p), A.base[wclass(a)], A.inv_scale);
+      f[a] = CD::dec(pop_load<NT>((const S*)p), A.base[wclass<Q>(a)], A.inv_scale);
     }
   }
 }
@@ -344,7 +341,7 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       bool wall;
       C term;
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
-      pop_store((S*)(p0 + A.pofs[o]), enc_step<ST, SR>(A, f[a] - term, o, h, a));
+      pop_store((S*)(p0 + A.pofs[o]), enc_step<Q, ST, SR>(A, f[a] - term, o, h, a));
     }
   } else {
     const char* const px[2] = {p0 + (long long)b.ox[0] * (long long)sizeof(S),
@@ -358,7 +355,7 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
       const char* nb = link_ptr<S, GEN>(A, b, p0, px, L::cx[a], L::cy[a], L::cz[a], off, slot, a);
       char* p = const_cast<char*>(wall ? p0 + A.pofs[o] : nb);
-      pop_store((S*)p, enc_step<ST, SR>(A, f[a] - term, o, h, a));
+      pop_store((S*)p, enc_step<Q, ST, SR>(A, f[a] - term, o, h, a));
     }
   }
 }
@@ -497,6 +494,10 @@ hipError_t launch_step_bgk(int q, int storage, int mode, bool forced, const void
     if (storage == ST_F64) return step_q_st<18, ST_F64, true>(mode, forced, args, s);
     if (storage == ST_F32) return step_q_st<18, ST_F32, true>(mode, forced, args, s);
     if (storage == ST_F16) return step_q_st<18, ST_F16, true>(mode, forced, args, s);
+  } else if (q == 26) {
+    if (storage == ST_F64) return step_q_st<26, ST_F64, true>(mode, forced, args, s);
+    if (storage == ST_F32) return step_q_st<26, ST_F32, true>(mode, forced, args, s);
+    if (storage == ST_F16) return step_q_st<26, ST_F16, true>(mode, forced, args, s);
   }
   return hipErrorInvalidValue;
 }
@@ -512,6 +513,10 @@ hipError_t launch_step(int q, int storage, int mode, bool forced, const void* ar
     if (storage == ST_F64) return step_q_st<18, ST_F64>(mode, forced, args, s);
     if (storage == ST_F32) return step_q_st<18, ST_F32>(mode, forced, args, s);
     if (storage == ST_F16) return step_q_st<18, ST_F16>(mode, forced, args, s);
+  } else if (q == 26) {
+    if (storage == ST_F64) return step_q_st<26, ST_F64>(mode, forced, args, s);
+    if (storage == ST_F32) return step_q_st<26, ST_F32>(mode, forced, args, s);
+    if (storage == ST_F16) return step_q_st<26, ST_F16>(mode, forced, args, s);
   }
   return hipErrorInvalidValue;
 }
@@ -554,7 +559,12 @@ __global__ __launch_bounds__(256) void k_set_pop(LatticeArgs<typename Codec<ST>:
   using C = typename CD::C;
   const long long N = (long long)A.nx * A.ny * A.nz;
   typename CD::S* dst = static_cast<typename CD::S*>(A.f) + a * A.stride;
-  const C base = A.base_s[wclass(a)];
+  // weight class of population a, selected without indexing by a
+  int cls = 0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (k == a) cls = wclass<Q>(k);
+  const C base = A.base_s[cls];
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
        n += (long long)gridDim.x * blockDim.x)
     dst[n] = CD::enc((C)in[n], base, A.scale);
@@ -585,7 +595,7 @@ __global__ __launch_bounds__(256) void k_init_eq(LatticeArgs<typename Codec<ST>:
       const double w = weight<Q>(a);
       const double cu = L::cx[a] * jx + L::cy[a] * jy + L::cz[a] * jz;
       const double fe = 3.0 * w * pn + w * (3.0 * cu + 4.5 * cu * cu - 1.5 * jsq);
-      dst[a * A.stride + n] = CD::enc((C)fe, A.base_s[wclass(a)], A.scale);
+      dst[a * A.stride + n] = CD::enc((C)fe, A.base_s[wclass<Q>(a)], A.scale);
     }
   }
 }
@@ -607,6 +617,10 @@ static int aux_blocks(long long N) {
       if ((st) == ST_F64) { constexpr int Q_ = 18; constexpr int ST_ = ST_F64; CALL; } \
       if ((st) == ST_F32) { constexpr int Q_ = 18; constexpr int ST_ = ST_F32; CALL; } \
       if ((st) == ST_F16) { constexpr int Q_ = 18; constexpr int ST_ = ST_F16; CALL; } \
+    } else if ((q) == 26) {                            \
+      if ((st) == ST_F64) { constexpr int Q_ = 26; constexpr int ST_ = ST_F64; CALL; } \
+      if ((st) == ST_F32) { constexpr int Q_ = 26; constexpr int ST_ = ST_F32; CALL; } \
+      if ((st) == ST_F16) { constexpr int Q_ = 26; constexpr int ST_ = ST_F16; CALL; } \
     }                                                  \
     return hipErrorInvalidValue;                       \
   } while (0)
@@ -695,7 +709,7 @@ __device__ __forceinline__ void store_node(const LatticeArgs<typename Codec<ST>:
   if (PHASE == 0) {
 #pragma unroll
     for (int a = 0; a < Q; ++a)
-      if (sel & (1u << a)) pop_store(dst + a * st + n, enc_any<ST>(A, f[a], a, h, a));
+      if (sel & (1u << a)) pop_store(dst + a * st + n, enc_any<Q, ST>(A, f[a], a, h, a));
   } else {
     const Nbr b = make_nbr<true>(A, x, y, z);
 #pragma unroll
@@ -707,7 +721,7 @@ __device__ __forceinline__ void store_node(const LatticeArgs<typename Codec<ST>:
       C term;
       link<Q, C>(b, A, o, -L::cx[a], -L::cy[a], -L::cz[a], off, wall, term, slot);
       const long long idx = wall ? (a * st + n) : (slot * st + (long long)(n + off));
-      pop_store(dst + idx, enc_any<ST>(A, f[a], a, h, a));
+      pop_store(dst + idx, enc_any<Q, ST>(A, f[a], a, h, a));
     }
   }
 }
@@ -1023,9 +1037,14 @@ hipError_t launch_monitor(int q, int storage, int phase, const void* args, void*
   DISPATCH_QST(q, storage, return (monitor_impl<Q_, ST_>(phase, args, snap, partial, nbo, s)));
 }
 
-// Pass 2: one workgroup, fixed-order sum of nb partial triples.
+// Pass 2: one workgroup, fixed-order sum of nb partial triples into
+// out[0..2], and out[3], a flag that stays 1 once any pass has seen a
+// non-finite sum |u| or mass, or (flags bit 0: the snapshot holds an
+// earlier u of this state) a non-finite sum |u - snap|; flags bit 1 starts
+// the flag afresh (the first pass on new memory or a replaced state).
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial,
-                                                         int nb, double* __restrict__ out) {
+                                                         int nb, double* __restrict__ out,
+                                                         int flags) {
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < nb; i += 256) {
     a += partial[3 * i];
@@ -1034,15 +1053,19 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
   }
   block_sum3(a, b, c);
   if (threadIdx.x == 0) {
+    const bool bad = !isfinite(b) || !isfinite(c) || ((flags & 1) && !isfinite(a));
+    const bool before = !(flags & 2) && out[3] != 0.0;
     out[0] = a;
     out[1] = b;
     out[2] = c;
+    out[3] = (bad || before) ? 1.0 : 0.0;
   }
 }
 
-hipError_t launch_reduce_partials(const double* partial, int nb, double* out, hipStream_t s) {
+hipError_t launch_reduce_partials(const double* partial, int nb, double* out, int flags,
+                                  hipStream_t s) {
   clear_stale_error();
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partial, nb, out, flags);
   return hipGetLastError();
 }
 
@@ -1213,6 +1236,10 @@ hipError_t launch_batch_group(int q, int storage, int mode, bool forced, const B
     batch_launch_m<18, ST_F32>(mode, forced, L, s);
   else if (q == 18 && storage == ST_F16)
     batch_launch_m<18, ST_F16>(mode, forced, L, s);
+  else if (q == 26 && storage == ST_F32)
+    batch_launch_m<26, ST_F32>(mode, forced, L, s);
+  else if (q == 26 && storage == ST_F16)
+    batch_launch_m<26, ST_F16>(mode, forced, L, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1288,6 +1315,10 @@ hipError_t launch_batch_nee(int q, int storage, int phase, const BatchMember* me
     batch_nee_q<18, ST_F32>(phase, members, nmembers, ntab, substep, total, s);
   else if (q == 18 && storage == ST_F16)
     batch_nee_q<18, ST_F16>(phase, members, nmembers, ntab, substep, total, s);
+  else if (q == 26 && storage == ST_F32)
+    batch_nee_q<26, ST_F32>(phase, members, nmembers, ntab, substep, total, s);
+  else if (q == 26 && storage == ST_F16)
+    batch_nee_q<26, ST_F16>(phase, members, nmembers, ntab, substep, total, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1330,13 +1361,21 @@ __global__ __launch_bounds__(256) void k_batch_monitor(const BatchMember* __rest
       if (ph == 0) monitor_body<14, ST_F16, 0>(A, snap, lb, nblk, a, b, c);
       else monitor_body<14, ST_F16, 1>(A, snap, lb, nblk, a, b, c);
     }
-  } else {
+  } else if (m.q == 18) {
     if (m.storage == ST_F32) {
       if (ph == 0) monitor_body<18, ST_F32, 0>(A, snap, lb, nblk, a, b, c);
       else monitor_body<18, ST_F32, 1>(A, snap, lb, nblk, a, b, c);
     } else {
       if (ph == 0) monitor_body<18, ST_F16, 0>(A, snap, lb, nblk, a, b, c);
       else monitor_body<18, ST_F16, 1>(A, snap, lb, nblk, a, b, c);
+    }
+  } else {
+    if (m.storage == ST_F32) {
+      if (ph == 0) monitor_body<26, ST_F32, 0>(A, snap, lb, nblk, a, b, c);
+      else monitor_body<26, ST_F32, 1>(A, snap, lb, nblk, a, b, c);
+    } else {
+      if (ph == 0) monitor_body<26, ST_F16, 0>(A, snap, lb, nblk, a, b, c);
+      else monitor_body<26, ST_F16, 1>(A, snap, lb, nblk, a, b, c);
     }
   }
   if (threadIdx.x == 0) {

@@ -37,7 +37,7 @@ template <typename C> struct LatticeArgs {
   void* g;                 // AB: the copy written this step; AA: == f
   long long stride;        // elements between population arrays (= N)
   long long pbytes;        // stride in bytes of the stored type
-  long long pofs[18];      // a * pbytes: byte offset of population array a
+  long long pofs[26];      // a * pbytes: byte offset of population array a
   int nx, ny, nz;
   int per_x, per_y, per_z; // periodic axes
   int sym;                 // bit f set: face f (-x,+x,-y,+y,-z,+z) is a
@@ -46,13 +46,13 @@ template <typename C> struct LatticeArgs {
   int xcd_order;           // tile order (workgroup w runs on XCD w % 8):
                            // 0 tile = w; 1 a contiguous range of tiles per
                            // XCD; 2 chunks of 4 tiles per XCD in turn
-  C sN[18], hN[18];        // s_k/N_k, (1 - s_k/2)/N_k
-  C bb[18][3];             // 6 w_a (c_a . u_w) for link a leaving through
+  C sN[26], hN[26];        // s_k/N_k, (1 - s_k/2)/N_k
+  C bb[26][3];             // 6 w_a (c_a . u_w) for link a leaving through
                            // the x / y / z face it crosses
   C F[3];                  // body force at this step
-  C base[2], base_s[2];    // FP16 deviation base 3 w_a p0 of the axis (a < 6)
-                           // and the other populations, and base 2^s (exact:
-                           // 2^s is a power of two); w_a takes two values
+  C base[3], base_s[3];    // FP16 deviation base 3 w_a p0 of the axis, edge
+                           // and corner populations (|c_a|^2 = 1, 2, 3), and
+                           // base 2^s (exact: 2^s is a power of two)
   C scale, inv_scale;      // FP16 2^s, 2^-s
   unsigned tstep;          // time level t of this step (FP16 rounding dither)
   int f16_sr;              // FP16 stores: 1 stochastic rounding, 0 nearest
@@ -100,8 +100,10 @@ hipError_t launch_macros(int q, int storage, int phase, const void* args, double
 // nblocks is returned through *nblocks_out (host computed).
 hipError_t launch_monitor(int q, int storage, int phase, const void* args, void* snap,
                           double* partial, int* nblocks_out, hipStream_t stream);
-// Monitor pass 2: fixed-order sum of the partials into out[3].
-hipError_t launch_reduce_partials(const double* partial, int nblocks, double* out,
+// Monitor pass 2: fixed-order sum of the partials into out[0..2]; out[3]
+// is a sticky non-finite flag (flags bit 0: count a non-finite sum |u - snap|
+// too; bit 1: start the flag afresh).
+hipError_t launch_reduce_partials(const double* partial, int nblocks, double* out, int flags,
                                   hipStream_t stream);
 int monitor_blocks(long long nodes);
 hipError_t launch_copy_probe(void* dst, const void* src, size_t bytes, int xcd, hipStream_t stream);

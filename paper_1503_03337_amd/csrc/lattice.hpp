@@ -1,15 +1,17 @@
 // lattice.hpp -- compile-time lattices and the MRT collision of the
 // incompressible D3Q14 / D3Q18 models (arXiv 1503.03337, Sec. 3 and
-// Appendix B), written for gfx950.
+// Appendix B) and of the 26-velocity model the closing paragraph of
+// Appendix B names (built by Sec. 3's construction), written for gfx950.
 //
 // The transforms m = T f and f* = f - T' N^-1 D are not stored as matrices:
-// both T's factor into sums/differences of opposite axis pairs and small
-// Walsh-Hadamard butterflies over the diagonal velocities (the 8 corners of
-// q = 14 form one 3-level butterfly; the 12 edges of q = 18 form three
-// 2-level ones, one per coordinate plane).  Each moment below is written as
-// a combination of those partial sums; the combinations follow the rows of
-// Eq. (T14) and of the 18x18 T of Appendix B.  No MFMA: every entry of T is
-// a small integer, so the transform is ~100-170 add/sub per node.
+// every T here factors into sums/differences of opposite axis pairs and
+// small Walsh-Hadamard butterflies over the diagonal velocities (the 8
+// corners form one 3-level butterfly; the 12 edges three 2-level ones, one
+// per coordinate plane).  Each moment below is written as a combination of
+// those partial sums; the combinations follow the rows of Eq. (T14), of the
+// 18x18 T of Appendix B and of the 26x26 T of the 26-velocity model.  No
+// MFMA: every entry of T is a small integer, so the transform is ~100-250
+// add/sub per node.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -24,8 +26,9 @@ template <> struct Lattice<14> {
   static constexpr int cy[14] = {0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
   static constexpr int cz[14] = {0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
   static constexpr int opp[14] = {1, 0, 3, 2, 5, 4, 13, 12, 11, 10, 9, 8, 7, 6};
-  // D3Q15 weights without the rest velocity (rest weight 2/9).
-  static constexpr double w_axis = 1.0 / 9.0, w_diag = 1.0 / 72.0, w0 = 2.0 / 9.0;
+  // D3Q15 weights without the rest velocity (rest weight 2/9), by |c|^2.
+  static constexpr double w_len[4] = {0.0, 1.0 / 9.0, 0.0, 1.0 / 72.0};
+  static constexpr double w0 = 2.0 / 9.0;
   // squared row norms of T (T T' = diag(N))
   static constexpr int N[14] = {14, 168, 10, 40, 10, 40, 10, 40, 12, 4, 8, 8, 8, 8};
 };
@@ -37,16 +40,46 @@ template <> struct Lattice<18> {
   static constexpr int cy[18] = {0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
   static constexpr int cz[18] = {0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
   static constexpr int opp[18] = {1, 0, 3, 2, 5, 4, 9, 8, 7, 6, 13, 12, 11, 10, 17, 16, 15, 14};
-  static constexpr double w_axis = 1.0 / 18.0, w_diag = 1.0 / 36.0, w0 = 1.0 / 3.0;
+  static constexpr double w_len[4] = {0.0, 1.0 / 18.0, 1.0 / 36.0, 0.0};
+  static constexpr double w0 = 1.0 / 3.0;
   static constexpr int N[18] = {18, 36, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
 };
 
+// The 26-velocity model: the 18 velocities of Appendix B in their order,
+// then the 8 corners in the order of Sec. 3; D3Q27 weights (rest 8/27).
+template <> struct Lattice<26> {
+  static constexpr int q = 26;
+  static constexpr int cx[26] = {1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                 1, -1, 1, -1, 1, -1, 1, -1};
+  static constexpr int cy[26] = {0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                 1, 1, -1, -1, 1, 1, -1, -1};
+  static constexpr int cz[26] = {0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1,
+                                 1, 1, 1, 1, -1, -1, -1, -1};
+  static constexpr int opp[26] = {1, 0, 3, 2, 5, 4, 9, 8, 7, 6, 13, 12, 11, 10, 17, 16, 15, 14,
+                                  25, 24, 23, 22, 21, 20, 19, 18};
+  static constexpr double w_len[4] = {0.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+  static constexpr double w0 = 8.0 / 27.0;
+  static constexpr int N[26] = {26, 2340, 360, 18, 72, 72, 18, 72, 72, 18, 72, 72, 36,
+                                72, 12,   24,  12, 12, 12, 24, 24, 24, 8,  8,  8,  8};
+};
+
+// |c_a|^2 (1 axis, 2 edge, 3 corner).
+template <int Q>
+__host__ __device__ constexpr int len2(int a) {
+  return Lattice<Q>::cx[a] * Lattice<Q>::cx[a] + Lattice<Q>::cy[a] * Lattice<Q>::cy[a] +
+         Lattice<Q>::cz[a] * Lattice<Q>::cz[a];
+}
+
 template <int Q>
 __host__ __device__ constexpr double weight(int a) {
-  return (Lattice<Q>::cx[a] * Lattice<Q>::cx[a] + Lattice<Q>::cy[a] * Lattice<Q>::cy[a] +
-          Lattice<Q>::cz[a] * Lattice<Q>::cz[a]) == 1
-             ? Lattice<Q>::w_axis
-             : Lattice<Q>::w_diag;
+  return Lattice<Q>::w_len[len2<Q>(a)];
+}
+
+// Weight class of population a: 0 axis, 1 edge, 2 corner (the FP16
+// deviation base 3 w_a p0 depends on nothing else).
+template <int Q>
+__host__ __device__ constexpr int wclass(int a) {
+  return len2<Q>(a) - 1;
 }
 
 // Index of the velocity equal to c_a with the components of the axes in
@@ -74,8 +107,8 @@ __device__ __forceinline__ double fma2(double k, double x, double y) { return __
 //   sN_k = s_k / N_k,   hN_k = (1 - s_k/2) / N_k,
 // so that d_k = D_k / N_k = sN_k (m_k - meq_k) - hN_k mF_k.
 template <typename C> struct Relax {
-  C sN[18];
-  C hN[18];
+  C sN[26];
+  C hN[26];
 };
 
 // ---------------------------------------------------------------------------
@@ -328,6 +361,214 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// 26-velocity model.  Moments (Gram-Schmidt of the monomial rows by tensor
+// order, Sec. 3's construction):
+//   0 P, 1 e, 2 eps, 3 jx, 4 qx, 5 hx, 6 jy, 7 qy, 8 hy, 9 jz, 10 qz, 11 hz,
+//   12 3pxx, 13 3pixx, 14 pww, 15 piww, 16 pxy, 17 pyz, 18 pxz, 19 pixy,
+//   20 piyz, 21 pixz, 22 tx, 23 ty, 24 tz, 25 txyz.
+// Basis rows: 1, 13|c|^2 - 27, (15|c|^4 - 61|c|^2 + 54)/2; c, (3|c|^2 - 7) c,
+// (9|c|^4 - 39|c|^2 + 38) c / 2; 3c_x^2 - |c|^2, c_y^2 - c_z^2 and these
+// times (3|c|^2 - 5); c_x c_y (...) and these times (3|c|^2 - 8); the
+// third-order t rows of Appendix B and c_x c_y c_z.  Equilibria (T f_eq with
+// the D3Q27 weights): P 19p/9 + 4|u|^2/9, e -18p + |u|^2, eps 3p - |u|^2,
+// j u, q -2u, h u, the stresses as for 18 velocities with pi = -p, t 0.
+// ---------------------------------------------------------------------------
+template <typename C, bool FORCED>
+__device__ __forceinline__ void collide26(C (&f)[26], const Relax<C>& r, const C (&F)[3]) {
+  const C ax = f[0] + f[1], dx = f[0] - f[1];
+  const C ay = f[2] + f[3], dy = f[2] - f[3];
+  const C az = f[4] + f[5], dz = f[4] - f[5];
+  const C A = ax + ay + az;
+  // edges 6..17, per plane (as for 18 velocities)
+  C s = f[6] + f[7], d = f[6] - f[7], s_ = f[8] + f[9], d_ = f[8] - f[9];
+  const C Sxy = s + s_, Yxy = s - s_, Xxy = d + d_, XYxy = d - d_;
+  s = f[10] + f[11];
+  d = f[10] - f[11];
+  s_ = f[12] + f[13];
+  d_ = f[12] - f[13];
+  const C Sxz = s + s_, Zxz = s - s_, Xxz = d + d_, XZxz = d - d_;
+  s = f[14] + f[15];
+  d = f[14] - f[15];
+  s_ = f[16] + f[17];
+  d_ = f[16] - f[17];
+  const C Syz = s + s_, Zyz = s - s_, Yyz = d + d_, YZyz = d - d_;
+  // corners 18..25 (as for 14 velocities): x, then y, then z
+  const C cs1 = f[18] + f[19], cd1 = f[18] - f[19];
+  const C cs2 = f[20] + f[21], cd2 = f[20] - f[21];
+  const C cs3 = f[22] + f[23], cd3 = f[22] - f[23];
+  const C cs4 = f[24] + f[25], cd4 = f[24] - f[25];
+  const C pp = cs1 + cs2, py = cs1 - cs2, px = cd1 + cd2, pxy = cd1 - cd2;
+  const C mp = cs3 + cs4, my = cs3 - cs4, mx = cd3 + cd4, mxy = cd3 - cd4;
+  const C K0 = pp + mp, Kz = pp - mp, Ky = py + my, Kyz = py - my;
+  const C Kx = px + mx, Kxz = px - mx, Kxy = pxy + mxy, Kxyz = pxy - mxy;
+
+  const C E = Sxy + Sxz + Syz;
+  const C mP = A + E + K0;
+  const C me = (C(-14) * A - E) + C(12) * K0;
+  const C meps = fma2(C(4), A - E, C(3) * K0);
+  const C ex = Xxy + Xxz, ey = Yxy + Yyz, ez = Zxz + Zyz;
+  const C jx = dx + ex + Kx, qx = fma2(C(-4), dx, fma2(C(2), Kx, -ex)),
+          hx = fma2(C(4), dx, fma2(C(-2), ex, Kx));
+  const C jy = dy + ey + Ky, qy = fma2(C(-4), dy, fma2(C(2), Ky, -ey)),
+          hy = fma2(C(4), dy, fma2(C(-2), ey, Ky));
+  const C jz = dz + ez + Kz, qz = fma2(C(-4), dz, fma2(C(2), Kz, -ez)),
+          hz = fma2(C(4), dz, fma2(C(-2), ez, Kz));
+  const C axis_xx = fma2(C(2), ax, -ay) - az;
+  const C edge_xx = fma2(C(-2), Syz, Sxy + Sxz);
+  const C pxx3 = axis_xx + edge_xx;
+  const C pixx3 = fma2(C(-2), axis_xx, edge_xx);
+  const C axis_ww = ay - az, edge_ww = Sxy - Sxz;
+  const C pww = axis_ww + edge_ww;
+  const C piww = fma2(C(-2), axis_ww, edge_ww);
+  const C mpxy = XYxy + Kxy, mpyz = YZyz + Kyz, mpxz = XZxz + Kxz;
+  const C mpixy = fma2(C(-2), XYxy, Kxy), mpiyz = fma2(C(-2), YZyz, Kyz),
+          mpixz = fma2(C(-2), XZxz, Kxz);
+  const C tx = Xxy - Xxz, ty = Yyz - Yxy, tz = Zxz - Zyz;
+
+  C ux = jx, uy = jy, uz = jz;
+  if (FORCED) {
+    ux = fma2(C(0.5), F[0], ux);
+    uy = fma2(C(0.5), F[1], uy);
+    uz = fma2(C(0.5), F[2], uz);
+  }
+  const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const C usq = uxx + uyy + uzz;
+  // Eq. (hgl) with w0 = 8/27: p = 9/19 (P - 4/9 |u|^2)
+  const C p = (mP - usq * C(4.0 / 9.0)) * C(9.0 / 19.0);
+  const C qxx = C(3) * uxx - usq, qww = uyy - uzz;
+  const C uxy = ux * uy, uyz = uy * uz, uxz = ux * uz;
+
+  C d0 = r.sN[0] * (mP - (C(19.0 / 9.0) * p + C(4.0 / 9.0) * usq));
+  C d1 = r.sN[1] * (me - (usq - C(18) * p));
+  C d2 = r.sN[2] * (meps - (C(3) * p - usq));
+  C d3 = r.sN[3] * (jx - ux);
+  C d4 = r.sN[4] * fma2(C(2), ux, qx);
+  C d5 = r.sN[5] * (hx - ux);
+  C d6 = r.sN[6] * (jy - uy);
+  C d7 = r.sN[7] * fma2(C(2), uy, qy);
+  C d8 = r.sN[8] * (hy - uy);
+  C d9 = r.sN[9] * (jz - uz);
+  C d10 = r.sN[10] * fma2(C(2), uz, qz);
+  C d11 = r.sN[11] * (hz - uz);
+  C d12 = r.sN[12] * (pxx3 - qxx);
+  C d13 = r.sN[13] * (pixx3 + qxx);
+  C d14 = r.sN[14] * (pww - qww);
+  C d15 = r.sN[15] * (piww + qww);
+  C d16 = r.sN[16] * (mpxy - uxy);
+  C d17 = r.sN[17] * (mpyz - uyz);
+  C d18 = r.sN[18] * (mpxz - uxz);
+  C d19 = r.sN[19] * (mpixy + uxy);
+  C d20 = r.sN[20] * (mpiyz + uyz);
+  C d21 = r.sN[21] * (mpixz + uxz);
+  C d22 = r.sN[22] * tx;
+  C d23 = r.sN[23] * ty;
+  C d24 = r.sN[24] * tz;
+  C d25 = r.sN[25] * Kxyz;
+  if (FORCED) {
+    // m_F = (d m_eq / d u) . F
+    const C Fx = F[0], Fy = F[1], Fz = F[2];
+    const C w = ux * Fx + uy * Fy + uz * Fz;
+    const C gxx = fma2(C(-2), w, C(6) * ux * Fx);
+    const C gww = C(2) * (uy * Fy - uz * Fz);
+    const C gxy = ux * Fy + uy * Fx, gyz = uy * Fz + uz * Fy, gxz = ux * Fz + uz * Fx;
+    d0 -= r.hN[0] * (C(8.0 / 9.0) * w);
+    d1 -= r.hN[1] * (C(2) * w);
+    d2 -= r.hN[2] * (C(-2) * w);
+    d3 -= r.hN[3] * Fx;
+    d4 -= r.hN[4] * (C(-2) * Fx);
+    d5 -= r.hN[5] * Fx;
+    d6 -= r.hN[6] * Fy;
+    d7 -= r.hN[7] * (C(-2) * Fy);
+    d8 -= r.hN[8] * Fy;
+    d9 -= r.hN[9] * Fz;
+    d10 -= r.hN[10] * (C(-2) * Fz);
+    d11 -= r.hN[11] * Fz;
+    d12 -= r.hN[12] * gxx;
+    d13 -= r.hN[13] * (-gxx);
+    d14 -= r.hN[14] * gww;
+    d15 -= r.hN[15] * (-gww);
+    d16 -= r.hN[16] * gxy;
+    d17 -= r.hN[17] * gyz;
+    d18 -= r.hN[18] * gxz;
+    d19 -= r.hN[19] * (-gxy);
+    d20 -= r.hN[20] * (-gyz);
+    d21 -= r.hN[21] * (-gxz);
+  }
+
+  // back-transform f*_a = f_a - sum_k T_ka d_k, axis velocities
+  const C bA = fma2(C(4), d2, C(-14) * d1 + d0);
+  const C X = fma2(C(4), d5 - d4, d3), Y = fma2(C(4), d8 - d7, d6),
+          Z = fma2(C(4), d11 - d10, d9);
+  const C xx = fma2(C(2), d12, C(-4) * d13);
+  const C yz_common = fma2(C(2), d13, -d12);
+  const C ww = fma2(C(-2), d15, d14);
+  const C yy = yz_common + ww, zz = yz_common - ww;
+  f[0] -= (bA + X) + xx;
+  f[1] -= (bA - X) + xx;
+  f[2] -= (bA + Y) + yy;
+  f[3] -= (bA - Y) + yy;
+  f[4] -= (bA + Z) + zz;
+  f[5] -= (bA - Z) + zz;
+  // edges: value(s1,s2) = W0 + s1 W1 + s2 W2 + s1 s2 W12 per plane
+  const C E0 = fma2(C(-4), d2, d0 - d1), G = d12 + d13, H = d14 + d15;
+  const C vx = fma2(C(-2), d5, d3 - d4), vy = fma2(C(-2), d8, d6 - d7),
+          vz = fma2(C(-2), d11, d9 - d10);
+  {  // xy plane (cx, cy)
+    const C W0 = E0 + G + H, W1 = vx + d22, W2 = vy - d23, W12 = fma2(C(-2), d19, d16);
+    C a = W0 + W2, b = W1 + W12;
+    f[6] -= a + b;
+    f[7] -= a - b;
+    a = W0 - W2;
+    b = W1 - W12;
+    f[8] -= a + b;
+    f[9] -= a - b;
+  }
+  {  // xz plane (cx, cz)
+    const C W0 = E0 + G - H, W1 = vx - d22, W2 = vz + d24, W12 = fma2(C(-2), d21, d18);
+    C a = W0 + W2, b = W1 + W12;
+    f[10] -= a + b;
+    f[11] -= a - b;
+    a = W0 - W2;
+    b = W1 - W12;
+    f[12] -= a + b;
+    f[13] -= a - b;
+  }
+  {  // yz plane (cy, cz)
+    const C W0 = fma2(C(-2), G, E0), W1 = vy + d23, W2 = vz - d24, W12 = fma2(C(-2), d20, d17);
+    C a = W0 + W2, b = W1 + W12;
+    f[14] -= a + b;
+    f[15] -= a - b;
+    a = W0 - W2;
+    b = W1 - W12;
+    f[16] -= a + b;
+    f[17] -= a - b;
+  }
+  // corners: inverse butterfly of W0 + cx Wx + cy Wy + cz Wz + cxcy Wxy + ...
+  const C W0 = C(3) * d2 + (C(12) * d1 + d0);
+  const C Wx = fma2(C(2), d4, d3 + d5), Wy = fma2(C(2), d7, d6 + d8),
+          Wz = fma2(C(2), d10, d9 + d11);
+  const C Wxy = d16 + d19, Wyz = d17 + d20, Wxz = d18 + d21;
+  const C zp0 = W0 + Wz, zpx = Wx + Wxz, zpy = Wy + Wyz, zpxy = Wxy + d25;
+  const C zm0 = W0 - Wz, zmx = Wx - Wxz, zmy = Wy - Wyz, zmxy = Wxy - d25;
+  C a = zp0 + zpy, b = zpx + zpxy;
+  f[18] -= a + b;
+  f[19] -= a - b;
+  a = zp0 - zpy;
+  b = zpx - zpxy;
+  f[20] -= a + b;
+  f[21] -= a - b;
+  a = zm0 + zmy;
+  b = zmx + zmxy;
+  f[22] -= a + b;
+  f[23] -= a - b;
+  a = zm0 - zmy;
+  b = zmx - zmxy;
+  f[24] -= a + b;
+  f[25] -= a - b;
+}
+
 // ---------------------------------------------------------------------------
 // Single-relaxation-time (LBGK) collision, the special case S = I/tau of the
 // MRT models (Sec. 3: Lambda-hat = I/tau gives the iD3Q15 LBGK model of
@@ -376,8 +617,10 @@ template <int Q, typename C, bool FORCED>
 __device__ __forceinline__ void collide(C (&f)[Q], const Relax<C>& r, const C (&F)[3]) {
   if constexpr (Q == 14)
     collide14<C, FORCED>(f, r, F);
-  else
+  else if constexpr (Q == 18)
     collide18<C, FORCED>(f, r, F);
+  else
+    collide26<C, FORCED>(f, r, F);
 }
 
 }  // namespace lbm

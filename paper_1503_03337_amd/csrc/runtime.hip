@@ -50,6 +50,9 @@ size_t population_bytes(int q, size_t N, int storage) {
   return (size_t)q * pop_stride(N) * (size_t)bytes_of(storage);
 }
 
+// Monitor runs whose results a context can hold unread (a ring).
+constexpr int kMonSlots = 8;
+
 bool is_nee_face(int kind) {
   return kind == LBM_VELOCITY || kind == LBM_PRESSURE || kind == LBM_SYMMETRY_NODE;
 }
@@ -69,7 +72,7 @@ long long nee_node_count(int nx, int ny, int nz, const lbm_spec* sp) {
 }
 
 std::string validate(int model, int nx, int ny, int nz, const double* s, const lbm_spec* sp) {
-  if (model != 14 && model != 18) return "model must be 14 or 18";
+  if (model != 14 && model != 18 && model != 26) return "model must be 14, 18 or 26";
   if (nx < 1 || ny < 1 || nz < 1) return "lattice dimensions must be >= 1";
   const long long N = (long long)nx * ny * nz;
   if (N >= (1LL << 31)) return "lattice too large (nx*ny*nz must be < 2^31)";
@@ -134,7 +137,7 @@ bool has_force(const lbm_spec& sp) {
 }
 
 template <int Q>
-void lattice_tables(int (&cx)[18], int (&cy)[18], int (&cz)[18], double (&w)[18], int (&N)[18]) {
+void lattice_tables(int (&cx)[26], int (&cy)[26], int (&cz)[26], double (&w)[26], int (&N)[26]) {
   for (int a = 0; a < Q; ++a) {
     cx[a] = Lattice<Q>::cx[a];
     cy[a] = Lattice<Q>::cy[a];
@@ -150,7 +153,7 @@ struct lbm_ctx {
   int q = 0, nx = 0, ny = 0, nz = 0;
   size_t N = 0;
   lbm_spec spec{};
-  double s[18] = {};
+  double s[26] = {};
   hipStream_t stream = nullptr;
   int device = 0;
   void* buf = nullptr;
@@ -169,8 +172,21 @@ struct lbm_ctx {
   long long t_snap = 0;
   long long mon_lag = 0;
   bool mon_ran = false;
-  bool mon_pending = false;
+  bool mon_pending = false;  // the last monitor run's sums are not yet read
   double mon[3] = {0, 0, 0};
+  // Monitor runs in flight: each copies its sums and the sticky flag into a
+  // slot of pinned host memory and records that slot's event, in a ring of
+  // kMonSlots, so that a poll can read the newest run that has completed
+  // while later ones are still queued.
+  double* h_mon = nullptr;                   // kMonSlots x 4 doubles
+  hipEvent_t mon_ev[kMonSlots] = {};
+  bool slot_pending[kMonSlots] = {};
+  long long slot_t[kMonSlots] = {};
+  int mon_next = 0;                          // slot of the next run
+  int mon_last = 0;                          // slot of the last run
+  bool mon_reset = true;        // the next run starts the device's non-finite flag afresh
+  bool tripped = false;         // a completed monitor run saw a non-finite value
+  long long trip_t = -1;        // ... in its run at this time level
   bool forced = false;
   int tx = 1, ty = 1;
   LatticeArgs<double> a64{};
@@ -247,18 +263,20 @@ int order_for(size_t bytes, bool batch) {
 
 template <typename C>
 void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
-  int cx[18], cy[18], cz[18], Nk[18];
-  double w[18];
+  int cx[26], cy[26], cz[26], Nk[26];
+  double w[26];
   if (c.q == 14)
     lattice_tables<14>(cx, cy, cz, w, Nk);
-  else
+  else if (c.q == 18)
     lattice_tables<18>(cx, cy, cz, w, Nk);
+  else
+    lattice_tables<26>(cx, cy, cz, w, Nk);
   std::memset(&A, 0, sizeof(A));
   A.f = c.popA;
   A.g = c.popB ? c.popB : c.popA;
   A.stride = (long long)pop_stride(c.N);
   A.pbytes = A.stride * (c.spec.storage == LBM_F64 ? 8 : c.spec.storage == LBM_F32 ? 4 : 2);
-  for (int a = 0; a < 18; ++a) A.pofs[a] = a * A.pbytes;
+  for (int a = 0; a < 26; ++a) A.pofs[a] = a * A.pbytes;
   A.nx = c.nx;
   A.ny = c.ny;
   A.nz = c.nz;
@@ -297,10 +315,16 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
   const double sc = std::ldexp(1.0, c.spec.f16_scale_log2);
   A.scale = (C)sc;
   A.inv_scale = (C)(1.0 / sc);
-  // one base per weight class: the axis populations (a < 6) and the rest
-  for (int k = 0; k < 2; ++k) {
-    A.base[k] = (C)(3.0 * w[k == 0 ? 0 : 6] * c.spec.p0);
-    A.base_s[k] = A.base[k] * A.scale;
+  // one base per weight class (|c_a|^2 = 1, 2, 3); classes a model lacks
+  // are never read
+  for (int k = 0; k < 3; ++k) {
+    A.base[k] = A.base_s[k] = 0;
+    for (int a = 0; a < c.q; ++a)
+      if (cx[a] * cx[a] + cy[a] * cy[a] + cz[a] * cz[a] == k + 1) {
+        A.base[k] = (C)(3.0 * w[a] * c.spec.p0);
+        A.base_s[k] = A.base[k] * A.scale;
+        break;
+      }
   }
   A.F[0] = A.F[1] = A.F[2] = 0;
   A.tstep = (unsigned)c.t;
@@ -353,15 +377,46 @@ int ensure_monitor(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// Pinned host slots for the monitor's sums and the events that say a slot
+// holds its run's values.
+int ensure_monitor_host(lbm_ctx* c) {
+  if (!c->h_mon)
+    HIPCHK(c, hipHostMalloc((void**)&c->h_mon, kMonSlots * 4 * sizeof(double),
+                            hipHostMallocDefault));
+  for (int s = 0; s < kMonSlots; ++s)
+    if (!c->mon_ev[s]) HIPCHK(c, hipEventCreateWithFlags(&c->mon_ev[s], hipEventDisableTiming));
+  return LBM_OK;
+}
+
+int trip_fail(lbm_ctx* c) {
+  return fail(c, LBM_ENONFINITE,
+              "the monitor found a non-finite value (run at t = " + std::to_string(c->trip_t) + ")");
+}
+
+// Queue a monitor run: the two reduction passes, then an asynchronous copy
+// of the sums and the sticky non-finite flag to pinned host memory.
 int run_monitor(lbm_ctx* c) {
   int rc = ensure_monitor(c);
+  if (!rc) rc = ensure_monitor_host(c);
   if (rc) return rc;
   set_force(*c, c->t);
   int nb = 0;
   const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
   HIPCHK(c, launch_monitor(c->q, c->spec.storage, phase, args_ptr(*c), c->snap, c->partial, &nb,
                            c->stream));
-  HIPCHK(c, launch_reduce_partials(c->partial, nb, c->d_res, c->stream));
+  const int flags = (c->snap_valid ? 1 : 0) | (c->mon_reset ? 2 : 0);
+  HIPCHK(c, launch_reduce_partials(c->partial, nb, c->d_res, flags, c->stream));
+  // a slot kMonSlots runs old that is still unread is reused: the flag the
+  // new run copies includes every earlier run's
+  const int slot = c->mon_next;
+  c->mon_next = (slot + 1) % kMonSlots;
+  HIPCHK(c, hipMemcpyAsync(c->h_mon + 4 * slot, c->d_res, 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipEventRecord(c->mon_ev[slot], c->stream));
+  c->slot_pending[slot] = true;
+  c->slot_t[slot] = c->t;
+  c->mon_last = slot;
+  c->mon_reset = false;
   c->mon_lag = c->snap_valid ? c->t - c->t_snap : 0;
   c->snap_valid = true;
   c->t_snap = c->t;
@@ -370,12 +425,51 @@ int run_monitor(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// Take over the values of a run whose copy has landed.
+void absorb_slot(lbm_ctx* c, int s) {
+  const double* h = c->h_mon + 4 * s;
+  for (int k = 0; k < 3; ++k) c->mon[k] = h[k];
+  if (h[3] != 0.0 && !c->tripped) {
+    c->tripped = true;
+    c->trip_t = c->slot_t[s];
+  }
+  c->slot_pending[s] = false;
+  if (s == c->mon_last) c->mon_pending = false;
+}
+
+// Read, oldest first, every run whose copy has landed; never waits (runs
+// complete in stream order, so the first one still in flight ends the scan).
+int poll_monitor(lbm_ctx* c) {
+  for (int i = 0; i < kMonSlots; ++i) {
+    const int s = (c->mon_next + i) % kMonSlots;
+    if (!c->slot_pending[s]) continue;
+    const hipError_t e = hipEventQuery(c->mon_ev[s]);
+    if (e == hipErrorNotReady) {
+      (void)hipGetLastError();
+      break;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventQuery(monitor)");
+    absorb_slot(c, s);
+  }
+  return LBM_OK;
+}
+
+// Wait for the last monitor run (not for later work on the stream).
 int fetch_monitor(lbm_ctx* c) {
   if (!c->mon_pending) return LBM_OK;
-  HIPCHK(c, hipMemcpyAsync(c->mon, c->d_res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipEventSynchronize(c->mon_ev[c->mon_last]));
+  return poll_monitor(c);
+}
+
+// A new state (lbm_set_f, lbm_init_fields): earlier monitor findings no
+// longer apply.
+void reset_monitor_state(lbm_ctx* c) {
+  c->snap_valid = false;
+  c->tripped = false;
+  c->trip_t = -1;
+  c->mon_reset = true;
   c->mon_pending = false;
-  return LBM_OK;
+  for (bool& p : c->slot_pending) p = false;
 }
 
 // RAII device scratch for the non-hot host-data paths.
@@ -401,8 +495,8 @@ void lbm_spec_default(lbm_spec* sp) {
 }
 
 size_t lbm_footprint_bytes(int model, int nx, int ny, int nz, const lbm_spec* sp) {
-  double s[18];
-  for (int k = 0; k < 18; ++k) s[k] = 1.0;
+  double s[26];
+  for (int k = 0; k < 26; ++k) s[k] = 1.0;
   if (!validate(model, nx, ny, nz, s, sp).empty()) return 0;
   const size_t N = (size_t)nx * ny * nz;
   size_t b = align_up(population_bytes(model, N, sp->storage));
@@ -659,6 +753,9 @@ extern "C" {
 int lbm_step(lbm_ctx* c, long long n) {
   if (!c) return LBM_EINVAL;
   if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+  int prc = poll_monitor(c);
+  if (prc) return prc;
+  if (c->tripped) return trip_fail(c);
   const long long K = c->spec.monitor_every;
   long long i = 0;
   const bool graphs = n >= kGraphSteps && graph_eligible(c);
@@ -677,6 +774,10 @@ int lbm_step(lbm_ctx* c, long long n) {
       i += 1;
     }
     if (K > 0 && c->t % K == 0) {
+      // the previous run's findings, if they have landed (no wait)
+      rc = poll_monitor(c);
+      if (rc) return rc;
+      if (c->tripped) return trip_fail(c);
       rc = run_monitor(c);
       if (rc) return rc;
     }
@@ -735,6 +836,32 @@ int lbm_residual(lbm_ctx* c, double* r) {
   return LBM_OK;
 }
 
+int lbm_residual_change(lbm_ctx* c, double* r, long long* lag) {
+  if (!c || !r) return LBM_EINVAL;
+  if (!c->mon_ran) return fail(c, LBM_ESTATE, "the monitor has not run");
+  int rc = fetch_monitor(c);
+  if (rc) return rc;
+  const bool lagged = c->mon_lag > 0;
+  if (lag) *lag = c->mon_lag;
+  if ((lagged && !std::isfinite(c->mon[0])) || !std::isfinite(c->mon[1]) ||
+      !std::isfinite(c->mon[2])) {
+    *r = std::numeric_limits<double>::quiet_NaN();
+    return fail(c, LBM_ENONFINITE, "monitor found a non-finite value");
+  }
+  if (!lagged || !(c->mon[1] > 0.0))
+    *r = std::numeric_limits<double>::infinity();
+  else
+    *r = c->mon[0] / c->mon[1];
+  return LBM_OK;
+}
+
+int lbm_poll(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  const int rc = poll_monitor(c);
+  if (rc) return rc;
+  return c->tripped ? trip_fail(c) : LBM_OK;
+}
+
 int lbm_mass(lbm_ctx* c, double* m) {
   if (!c || !m) return LBM_EINVAL;
   if (!c->mon_ran) {
@@ -776,7 +903,7 @@ int lbm_set_f(lbm_ctx* c, const double* f) {
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
-  c->snap_valid = false;
+  reset_monitor_state(c);
   return LBM_OK;
 }
 
@@ -796,7 +923,7 @@ int lbm_init_fields(lbm_ctx* c, const double* p, const double* u) {
   HIPCHK(c, launch_init_eq(c->q, c->spec.storage, args_ptr(*c), (const double*)tp.p,
                            (const double*)tu.p, c->spec.p0, c->spec.u0, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->snap_valid = false;
+  reset_monitor_state(c);
   return LBM_OK;
 }
 
@@ -857,6 +984,12 @@ int lbm_destroy(lbm_ctx* c) {
   if ((c->own_buf && c->buf) || c->mon_buf) (void)hipStreamSynchronize(c->stream);
   if (c->own_buf && c->buf) (void)hipFree(c->buf);
   if (c->mon_buf) (void)hipFree(c->mon_buf);
+  for (hipEvent_t& ev : c->mon_ev)
+    if (ev) {
+      (void)hipEventSynchronize(ev);  // its copy writes into h_mon
+      (void)hipEventDestroy(ev);
+    }
+  if (c->h_mon) (void)hipHostFree(c->h_mon);
   for (auto& g : c->gexec)
     if (g) (void)hipGraphExecDestroy(g);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -1042,16 +1175,17 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   // One specialised launch per (q, storage) class and step.  For n >= 2 the
   // members run in step with the AA parity of the first active member (one
   // out of step sits out the first substep of this call); for n == 1 the
-  // parity is part of the class instead.  Class bits: 4 odd parity (n == 1
-  // only), 2 q18, 1 FP16.
-  constexpr int NG = 8;
+  // parity is part of the class instead.  Class index: 6 x odd parity
+  // (n == 1 only) + 2 x model (0: q = 14, 1: q = 18, 2: q = 26) + FP16.
+  constexpr int NG = 12;
   const bool align = n >= 2;
   const int parity = b->members[act[0]].ctx->phase;
   auto cls = [&](int i) {
     const lbm_ctx* c = b->members[i].ctx;
-    return (align ? 0 : (c->phase ? 4 : 0)) + (c->q == 18 ? 2 : 0) +
+    return (align ? 0 : (c->phase ? 6 : 0)) + 2 * (c->q == 14 ? 0 : c->q == 18 ? 1 : 2) +
            (c->spec.storage == LBM_F32 ? 0 : 1);
   };
+  auto cls_q = [](int k) { return (k % 6) < 2 ? 14 : (k % 6) < 4 ? 18 : 26; };
   std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return cls(x) < cls(y); });
   const int nm = (int)act.size();
   int cls_off[NG] = {}, cls_cnt[NG] = {}, cls_forced[NG] = {};
@@ -1191,7 +1325,7 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   for (long long s = 0; s < nmax; ++s)
     for (int k = 0; k < NG; ++k) {
       if (cls_cnt[k] == 0 || s >= cls_steps[k]) continue;
-      const int odd = (int)(((align ? parity : (k >> 2)) + s) & 1);
+      const int odd = (int)(((align ? parity : k / 6) + s) & 1);
       BatchLaunch L;
       L.members = b->d_members + cls_off[k];
       L.nmembers = cls_cnt[k];
@@ -1200,11 +1334,11 @@ int lbm_batch_step(lbm_batch* b, long long n) {
       L.ftab = b->d_ftab;
       L.substep = (int)s;
       L.xcd_order = xcd;
-      BHIP(b, launch_batch_group((k & 2) ? 18 : 14, (k & 1) ? ST_F16 : ST_F32,
+      BHIP(b, launch_batch_group(cls_q(k), (k & 1) ? ST_F16 : ST_F32,
                                  odd ? MODE_AA_ODD : MODE_AA_EVEN, cls_forced[k] != 0, L,
                                  b->stream));
       if (cls_nee[k] > 0)
-        BHIP(b, launch_batch_nee((k & 2) ? 18 : 14, (k & 1) ? ST_F16 : ST_F32, odd ? 0 : 1,
+        BHIP(b, launch_batch_nee(cls_q(k), (k & 1) ? ST_F16 : ST_F32, odd ? 0 : 1,
                                  b->d_members + cls_off[k], cls_cnt[k], b->d_ntab, (int)s,
                                  cls_nee[k], b->stream));
     }
@@ -1289,9 +1423,16 @@ int lbm_batch_monitor(lbm_batch* b) {
   BHIP(b, hipStreamSynchronize(b->stream));
   for (int j = 0; j < nm; ++j) {
     lbm_ctx* c = mons[j];
+    (void)poll_monitor(c);  // earlier single runs, all done (stream synchronised)
     c->mon[0] = res[3 * j];
     c->mon[1] = res[3 * j + 1];
     c->mon[2] = res[3 * j + 2];
+    const bool bad = !std::isfinite(c->mon[1]) || !std::isfinite(c->mon[2]) ||
+                     (c->snap_valid && !std::isfinite(c->mon[0]));
+    if (bad && !c->tripped) {
+      c->tripped = true;
+      c->trip_t = c->t;
+    }
     c->mon_lag = c->snap_valid ? c->t - c->t_snap : 0;
     c->snap_valid = true;
     c->t_snap = c->t;

@@ -26,6 +26,7 @@ COLLISION = {"mrt": 0, "bgk": 1}
 PATTERN = {"ab": 0, "aa": 1}
 FACE_KIND = {"periodic": 0, "wall": 1, "symmetry": 2, "velocity": 3, "pressure": 4,
              "symmetry_node": 5}
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
 
@@ -101,6 +102,8 @@ def lib():
             "lbm_macros": (i, [vp, dp, dp]),
             "lbm_macros_device": (i, [vp, vp, vp]),
             "lbm_residual": (i, [vp, dp]),
+            "lbm_residual_change": (i, [vp, dp, C.POINTER(ll)]),
+            "lbm_poll": (i, [vp]),
             "lbm_mass": (i, [vp, dp]),
             "lbm_monitor": (i, [vp]),
             "lbm_get_f": (i, [vp, dp]),
@@ -271,6 +274,24 @@ class Lattice:
         r = C.c_double()
         self._chk(lib().lbm_residual(self.h, C.byref(r)), "lbm_residual")
         return r.value
+
+    def residual_change(self):
+        """(R_L, L): the change of u over the monitor's lag L in the norm of
+        the paper's steady-state criteria (not divided by L)."""
+        r = C.c_double()
+        lag = C.c_longlong()
+        self._chk(lib().lbm_residual_change(self.h, C.byref(r), C.byref(lag)),
+                  "lbm_residual_change")
+        return r.value, int(lag.value)
+
+    def poll(self):
+        """Raise LbmError (LBM_ENONFINITE) if a completed monitor run has seen
+        a non-finite value; never waits for the device."""
+        self._chk(lib().lbm_poll(self.h), "lbm_poll")
+
+    def healthy(self):
+        """False once a completed monitor run has seen a non-finite value."""
+        return lib().lbm_poll(self.h) != ENONFINITE
 
     def mass(self):
         m = C.c_double()

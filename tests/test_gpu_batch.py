@@ -27,11 +27,16 @@ MEMBERS = [
      (0, 0, 0), 0.0),
     (14, (17, 12, 10), "f16dev", ("symmetry", "wall", "periodic", "periodic", "wall", "symmetry"),
      {"+x": (0, 0.04, 0.02)}, (1e-5, 0, 0), (0, 0, 0), 0.0),
+    # the 26-velocity model (Appendix B's closing paragraph)
+    (26, (21, 14, 9), "f32", ("wall",) * 6, {"+z": (0.08, 0, 0)}, (0, 0, 0), (0, 0, 0), 0.0),
+    (26, (15, 11, 13), "f16dev", ("periodic", "periodic", "wall", "wall", "wall", "symmetry"),
+     {"-y": (0.02, 0, 0.01)}, (2e-5, 0, 0), (1e-5, 0, 0), 11.0),
 ]
 
 
 def rates(q, k):
-    return svec(q, 1.3 + 0.1 * k) + np.linspace(-0.02, 0.02, q)
+    sn = 1.3 + 0.1 * k if k < 7 else 1.45 + 0.2 * (k - 7)  # s_nu < 2 for every member
+    return svec(q, sn) + np.linspace(-0.02, 0.02, q)
 
 
 def build(k, seed, monitor_every=0):
@@ -57,7 +62,7 @@ def run_alone(k, nsteps, seed, via_batch=True):
 
 
 def test_alone_equals_mix_bit_exact():
-    budgets = [7, 5, 9, 6, 8, 10, 4]
+    budgets = [7, 5, 9, 6, 8, 10, 4, 6, 9]
     alone = [run_alone(k, budgets[k], 100 + k) for k in range(len(MEMBERS))]
     lats = [build(k, 100 + k) for k in range(len(MEMBERS))]
     b = lbm.Batch(lats[0].stream)
@@ -75,10 +80,12 @@ def test_alone_equals_mix_bit_exact():
 
 
 def test_batch_equals_single_kernel():
+    """The batched step and the single-lattice step do the same arithmetic
+    per node: the same populations bit for bit."""
     for k in range(len(MEMBERS)):
         a = run_alone(k, 6, 200 + k, via_batch=True)
         s = run_alone(k, 6, 200 + k, via_batch=False)
-        assert np.linalg.norm(a - s) <= 1e-6 * np.linalg.norm(s), "member %d" % k
+        assert np.array_equal(a, s), "member %d" % k
 
 
 def test_batch_matches_oracle():
@@ -374,18 +381,32 @@ def test_large_single_lattice_orders_agree():
     """Beyond 384 MB a single lattice gives the XCDs chunks of 4 rows in turn
     and a batch chunks of 64 workgroups: a 180^3 D3Q18 FP32 lattice (420 MB;
     32,400 rows, so the last 16 workgroups keep their place) stepped alone
-    and as the only member of a batch gives the same populations bit for
-    bit, from random ones, after an even, an odd and another even step."""
+    matches the FP64 oracle run from the same (FP32-rounded) start after an
+    even and after an odd step (relative L2 1e-6), and stepped as the only
+    member of a batch gives the same populations bit for bit, from random
+    ones, after an even, an odd and another even step."""
     q, n = 18, 180
+    faces, lid = ("wall",) * 6, {"+z": (0.05, 0.02, 0.0)}
     pair = []
     for _ in range(2):
-        lat = lbm.Lattice(q, n, n, n, rates(q, 1), faces=("wall",) * 6,
-                          wall_u={"+z": (0.05, 0.02, 0.0)}, storage="f32", pattern="aa")
+        lat = lbm.Lattice(q, n, n, n, rates(q, 1), faces=faces, wall_u=lid, storage="f32",
+                          pattern="aa")
         lat.set_f(inputs.random_populations(q, n, n, n, seed=650))
         pair.append(lat)
     assert lbm.footprint_bytes(q, n, n, n, storage="f32", pattern="aa") > 384 << 20
     alone, member = pair
-    alone.step(3)
+    pr = R.problem(q, n, n, n, rates(q, 1), faces=faces, wall_u=lid)
+    ref = alone.get_f()
+    for t in range(2):  # the even step, then the odd one
+        alone.step(1)
+        ref = R.run(pr, ref, t, 1)
+        got = alone.get_f()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print("180^3 D3Q18 FP32, step %d (%s): rel L2 vs oracle %.2e"
+              % (t + 1, "even" if t == 0 else "odd", err))
+        assert err <= 1e-6, (t, err)
+        del got
+    alone.step(1)
     b = lbm.Batch(member.stream)
     b.add(member, 3)
     b.step(3)

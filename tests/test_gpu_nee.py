@@ -63,7 +63,7 @@ def make(q, setup, storage, pattern, seed=0):
     return lat, pr
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 @pytest.mark.parametrize("pattern", ("ab", "aa"))
 @pytest.mark.parametrize("setup", sorted(SETUPS))
 def test_fp64_matches_oracle(q, pattern, setup):
@@ -81,7 +81,7 @@ def test_fp64_matches_oracle(q, pattern, setup):
     lat.close()
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 @pytest.mark.parametrize("storage", ("f32", "f16dev"))
 @pytest.mark.parametrize("setup", sorted(SETUPS))
 def test_reduced_storage_matches_oracle(q, storage, setup):
@@ -97,7 +97,7 @@ def test_reduced_storage_matches_oracle(q, storage, setup):
     lat.close()
 
 
-@pytest.mark.parametrize("q", (14, 18))
+@pytest.mark.parametrize("q", (14, 18, 26))
 @pytest.mark.parametrize("storage", ("f64", "f32"))
 @pytest.mark.parametrize("setup", sorted(SETUPS))
 def test_aa_equals_ab_bit_exact(q, storage, setup):
@@ -118,7 +118,7 @@ def test_batched_faces_equal_single_lattices_bit_exact(storage):
     3 steps) and two members start at the other AA parity, so members sit
     out substeps and single-step calls take the parity into the class."""
     singles, members = [], []
-    for q in (14, 18):
+    for q in (14, 18, 26):
         for k, setup in enumerate(sorted(SETUPS)):
             for group in (singles, members):
                 lat, _ = make(q, setup, storage, "aa", seed=11 + k)

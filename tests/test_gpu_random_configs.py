@@ -28,10 +28,12 @@ FACE_NAMES = ("-x", "+x", "-y", "+y", "-z", "+z")
 NONPERIODIC = ("wall", "symmetry", "velocity", "pressure", "symmetry_node")
 NODE_BASED = ("velocity", "pressure", "symmetry_node")
 COUNT = 200
+COUNT26 = 60
 
 
-def random_config(rng):
-    q = int(rng.choice([14, 18]))
+def random_config(rng, q=None):
+    if q is None:
+        q = int(rng.choice([14, 18]))
     dims = [int(rng.integers(1, 14)) for _ in range(3)]
     if rng.random() < 0.3:
         dims[0] = int(rng.integers(60, 140))
@@ -62,10 +64,14 @@ def random_config(rng):
 
 def configs():
     rng = np.random.default_rng(20260)
-    return [random_config(rng) for _ in range(COUNT)]
+    out = [random_config(rng) for _ in range(COUNT)]
+    # the 26-velocity model on a sweep of its own (the first COUNT keep
+    # their draws)
+    rng26 = np.random.default_rng(2626)
+    return out + [random_config(rng26, q=26) for _ in range(COUNT26)]
 
 
-@pytest.mark.parametrize("i", range(COUNT))
+@pytest.mark.parametrize("i", range(COUNT + COUNT26))
 def test_random_config_fp64_matches_oracle(i):
     q, dims, s, kw = configs()[i]
     pattern = "aa" if i % 2 == 0 else "ab"
