@@ -21,7 +21,18 @@ admitted request down, so large requests run one after another (as in the
 plain server) while small ones, which cannot fill the GPU alone, share it.
 
 Latency is arrival -> finish.  Aggregate throughput is the node updates of
-all requests over the time from the first arrival to the last finish.
+all completed requests over the time from the first arrival to the last
+finish.
+
+Failure: every request runs the FP64 monitor (every 100 steps with a
+residual stop, else every 1000 steps); a request whose monitor sees a
+non-finite mass or velocity (a diverging solve: Sec. 4.3 reports the LBGK
+cavity diverging at Re 3200, and a 14-velocity MRT cavity with bounce-back
+walls does too) is retired at once with status "failed" and its memory
+freed, and the server keeps serving the others, whose results do not
+change.  A request that ends its budget gets one more monitor run first, so
+a result that turned non-finite after its last periodic run is reported as
+failed too.
 """
 import math
 import time
@@ -32,6 +43,8 @@ from . import autotune, inputs, lbm, params
 
 MONITOR_EVERY = 100   # residual lag (steps) for requests with a residual stop
 RESIDUAL_EVERY = 500  # a residual stop is checked when the request's t is a multiple
+HEALTH_EVERY = 1000   # monitor interval of the other requests (non-finite check)
+PLAIN_CHUNK = 1000    # steps per lbm_step call of the plain server
 DUCT_UMAX = 0.05      # centre-line speed of duct requests
 CAVITY_RE = 400.0     # cavity Reynolds number at lid speed 0.1
 DUCT_EFOLD = 1500.0   # slowest duct mode decays within this many steps
@@ -56,21 +69,22 @@ def duct_nu(edge):
 
 def request_setup(req):
     """Lattice of a request: a square duct (edge^3 nodes, x periodic, body
-    force for u_max = 0.05, odd rates tied to s_nu so that the wide ducts'
-    larger nu does not move the walls) or a lid-driven cube (lid 0.1 along
-    +x, the paper's rates)."""
+    force for u_max = 0.05; odd rates tied to s_nu so that the wide ducts'
+    larger nu does not move the walls, or with req["odd"] = "paper" the
+    paper's fixed s_q = 1.2, s_t = 0.98) or a lid-driven cube (lid 0.1 along
+    +x, Reynolds number req.get("Re", 400), the paper's rates)."""
     q, L = req["q"], req["edge"]
     if req["kind"] == "duct":
-        cfg = params.duct(q, L, L, duct_nu(L), umax=DUCT_UMAX, odd="magic")
+        cfg = params.duct(q, L, L, duct_nu(L), umax=DUCT_UMAX, odd=req.get("odd", "magic"))
         kw = {"faces": cfg["faces"], "F0": cfg["F0"]}
     else:
-        cfg = params.cavity(q, L, CAVITY_RE, lid=0.1)
+        cfg = params.cavity(q, L, req.get("Re", CAVITY_RE), lid=0.1)
         kw = {"faces": cfg["faces"], "wall_u": cfg["wall_u"]}
     return cfg["s_vec"], kw
 
 
 def _monitor(req):
-    return MONITOR_EVERY if req.get("stop_residual") else 0
+    return MONITOR_EVERY if req.get("stop_residual") else HEALTH_EVERY
 
 
 def footprint(req, storage):
@@ -99,34 +113,72 @@ def _finish(rec, clock, lat, keep_fields):
     rec["finish"] = clock.now()
     rec["latency"] = rec["finish"] - rec["arrival"]
     rec["steps_done"] = lat.time
-    if keep_fields:
+    rec.setdefault("status", "ok")
+    if keep_fields and rec["status"] == "ok":
         rec["u"] = lat.macros()[1]
 
 
-def serve_plain(trace, storage="f32", keep_fields=False):
-    """One request at a time in arrival order (FIFO), lbm_step."""
+def _final_check(rec, lat):
+    """One more monitor run at the request's end: a state that is not
+    finite fails the request."""
+    if rec.get("status", "ok") != "ok":
+        return
+    try:
+        lat.monitor()
+        lat.mass()  # waits for that run; raises LBM_ENONFINITE
+    except lbm.LbmError as e:
+        _failed(rec, e)
+
+
+def _failed(rec, err):
+    """Mark a request whose monitor saw a non-finite value; re-raise any
+    other error."""
+    if not (isinstance(err, lbm.LbmError) and err.code == lbm.ENONFINITE):
+        raise err
+    rec["status"] = "failed"
+    rec["error"] = str(err)
+
+
+def serve_plain(trace, storage="f32", keep_fields=False, on_admit=None):
+    """One request at a time in arrival order (FIFO), lbm_step in calls of
+    PLAIN_CHUNK steps with at most two in flight.  on_admit(rec, lat), if
+    given, is called with each new lattice before it steps."""
     import torch
     clock = Clock()
     out = []
+    stream = torch.cuda.current_stream()
     for req in sorted(trace, key=lambda r: r["arrival"]):
         while clock.now() < req["arrival"]:
             time.sleep(min(0.001, max(0.0, req["arrival"] - clock.now())))
         rec = dict(req)
         rec["admit"] = clock.now()
         lat = make_lattice(req, storage)
-        if req.get("stop_residual"):
-            # the monitor runs every MONITOR_EVERY steps inside lbm_step;
-            # the stop is checked every RESIDUAL_EVERY steps (lag 100)
-            done = 0
+        if on_admit:
+            on_admit(rec, lat)
+        # the monitor runs inside lbm_step (every MONITOR_EVERY steps with a
+        # residual stop, checked every RESIDUAL_EVERY steps at lag 100; else
+        # every HEALTH_EVERY steps); lbm_step raises LBM_ENONFINITE once a
+        # completed run saw a non-finite value
+        try:
+            done, inflight = 0, []
+            chunk = RESIDUAL_EVERY if req.get("stop_residual") else PLAIN_CHUNK
             while done < req["steps"]:
-                k = min(RESIDUAL_EVERY, req["steps"] - done)
+                k = min(chunk, req["steps"] - done)
                 lat.step(k)
                 done += k
-                if done % RESIDUAL_EVERY == 0 and lat.residual() <= req["stop_residual"]:
-                    break
-        else:
-            lat.step(req["steps"])
-        torch.cuda.current_stream().synchronize()
+                if req.get("stop_residual"):
+                    if done % RESIDUAL_EVERY == 0 and lat.residual() <= req["stop_residual"]:
+                        break
+                else:
+                    ev = torch.cuda.Event()
+                    ev.record(stream)
+                    inflight.append(ev)
+                    if len(inflight) > 2:
+                        inflight.pop(0).synchronize()
+        except lbm.LbmError as e:
+            _failed(rec, e)
+        _final_check(rec, lat)
+        stream.synchronize()
         _finish(rec, clock, lat, keep_fields)
         lat.close()
         out.append(rec)
@@ -134,7 +186,8 @@ def serve_plain(trace, storage="f32", keep_fields=False):
 
 
 def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
-                  keep_fields=False, tiles=None, max_active_bytes=SATURATION_BYTES):
+                  keep_fields=False, tiles=None, max_active_bytes=SATURATION_BYTES,
+                  on_admit=None):
     """Continuous batching with admission by HBM footprint.
 
     The loop keeps the device busy: quantum k+1 is queued before the host
@@ -148,7 +201,15 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
     tiles: optional {(q, edge bucket): (tx, ty)} from autotune.tune.
     max_active_bytes: admission stops while the admitted lattices move this
     many bytes per step (a request is always admitted into an empty batch);
-    None admits whatever fits the memory budget."""
+    None admits whatever fits the memory budget.
+    Every member runs its monitor on its own clock (residual stops: a
+    snapshot and a check as above; other members every HEALTH_EVERY steps),
+    queued right after the quantum that reaches that time level; after each
+    quantum the host polls every member without waiting, and a member whose
+    completed monitor run saw a non-finite value leaves the batch at once,
+    reported with status "failed".
+    on_admit(rec, lat), if given, is called with each new lattice before it
+    joins the batch."""
     assert MONITOR_EVERY % quantum == 0 and RESIDUAL_EVERY % quantum == 0
     import torch
     clock = Clock()
@@ -165,6 +226,7 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
 
     def retire(rec, lat):
         nonlocal used
+        _final_check(rec, lat)
         _finish(rec, clock, lat, keep_fields)
         used -= rec.pop("_need")
         lat.close()
@@ -187,6 +249,8 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
             rec = dict(req)
             rec["admit"] = clock.now()
             lat = make_lattice(req, storage)
+            if on_admit:
+                on_admit(rec, lat)
             batch.add(lat, req["steps"])
             if tiles:
                 t = autotune.tile_for(tiles, req["q"], req["edge"])
@@ -208,15 +272,24 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
             inflight.append(ev)
             done = [(r, l) for r, l in active if batch.remaining(l) == 0]
             for r, l in active:
-                if not r.get("stop_residual") or batch.remaining(l) == 0:
+                if batch.remaining(l) == 0:
                     continue
                 t = l.time
-                if t % RESIDUAL_EVERY == RESIDUAL_EVERY - MONITOR_EVERY:
-                    l.monitor()  # snapshot, queued
-                elif t % RESIDUAL_EVERY == 0:
-                    l.monitor()
-                    if l.residual() <= r["stop_residual"]:  # synchronises
-                        done.append((r, l))
+                try:
+                    if not l.healthy():  # a completed monitor run saw a non-finite value
+                        l.poll()
+                    if not r.get("stop_residual"):
+                        if t % HEALTH_EVERY == 0:
+                            l.monitor()  # queued; its result is polled later
+                    elif t % RESIDUAL_EVERY == RESIDUAL_EVERY - MONITOR_EVERY:
+                        l.monitor()  # snapshot, queued
+                    elif t % RESIDUAL_EVERY == 0:
+                        l.monitor()
+                        if l.residual() <= r["stop_residual"]:  # waits for the monitor
+                            done.append((r, l))
+                except lbm.LbmError as e:
+                    _failed(r, e)
+                    done.append((r, l))
             for r, l in done:
                 batch.remove(l)
                 active_bytes -= step_bytes(r, storage)
@@ -245,11 +318,12 @@ def serve_batched(trace, storage="f16dev", budget_bytes=16 << 30, quantum=100,
 
 
 def summarise(records, extra=None):
-    lat = np.array([r["latency"] for r in records])
-    nodes = sum(r["edge"] ** 3 * r["steps_done"] for r in records)
+    ok = [r for r in records if r.get("status", "ok") == "ok"]
+    lat = np.array([r["latency"] for r in ok])
+    nodes = sum(r["edge"] ** 3 * r["steps_done"] for r in ok)
     t0 = min(r["arrival"] for r in records)
     t1 = max(r["finish"] for r in records)
-    out = {"requests": len(records),
+    out = {"requests": len(records), "failed": len(records) - len(ok),
            "p50_s": round(float(np.percentile(lat, 50)), 4),
            "p99_s": round(float(np.percentile(lat, 99)), 4),
            "aggregate_MLUPS": round(nodes / (t1 - t0) / 1e6, 1),
@@ -283,10 +357,18 @@ def duct_error(records, series):
                 if r["kind"] == "duct" and "u" in r), default=0.0)
 
 
+def _note(msg):
+    import sys
+    print("serve: " + msg, file=sys.stderr, flush=True)
+
+
 def bench_summary(n=24, seed=1, budget_gib=16):
-    """Plain FP32 against batched FP32 and FP16 deviations on one seeded
-    Poisson trace (rate ~0.8x the plain server's measured capacity), and on
-    the same requests all arriving at once (saturated)."""
+    """Plain FP32 and FP16 deviations against batched FP32 and FP16
+    deviations on one seeded Poisson trace (rate ~0.8x the plain FP32
+    server's measured capacity), and on the same requests all arriving at
+    once (saturated), so that the gain of batched FP16 over plain FP32 splits
+    into its storage part (plain FP16 / plain FP32) and its batching part
+    (batched FP16 / plain FP16)."""
     import torch
     trace = inputs.serving_trace(n, rate=1.0, seed=seed)
     # plain-server capacity from a short probe of the same request mix
@@ -308,24 +390,39 @@ def bench_summary(n=24, seed=1, budget_gib=16):
     res = {"trace": {"requests": n, "rate_per_s": round(rate, 3), "seed": seed,
                      "budget_GiB": budget_gib}}
     res["plain_f32"] = summarise(*serve_plain(trace, "f32"))
+    _note("plain_f32 done")
+    res["plain_f16dev"] = summarise(*serve_plain(trace, "f16dev"))
+    _note("plain_f16dev done")
     res["batched_f32"] = summarise(*serve_batched(trace, "f32", budget, tiles=tiles))
+    _note("batched_f32 done")
     res["batched_f16dev"] = summarise(*serve_batched(trace, "f16dev", budget, tiles=tiles))
+    _note("batched_f16dev done")
     sat = [dict(r, arrival=0.0) for r in trace]
     res["saturated_plain_f32"] = summarise(*serve_plain(sat, "f32"))
+    _note("saturated_plain_f32 done")
+    res["saturated_plain_f16dev"] = summarise(*serve_plain(sat, "f16dev"))
+    _note("saturated_plain_f16dev done")
+    res["saturated_batched_f32"] = summarise(*serve_batched(sat, "f32", budget, tiles=tiles))
+    _note("saturated_batched_f32 done")
     res["saturated_batched_f16dev"] = summarise(*serve_batched(sat, "f16dev", budget,
                                                                tiles=tiles))
+    _note("saturated_batched_f16dev done")
     res["duct_accuracy"] = duct_accuracy()
+    _note("duct accuracy done")
+    res["duct_accuracy_paper_odd_rates"] = duct_accuracy(odd="paper")
     torch.cuda.synchronize()
     return res
 
 
-def duct_accuracy(edges=(32, 64, 96, 128, 160), steps=20000):
+def duct_accuracy(edges=(32, 64, 96, 128, 160), steps=20000, odd="magic"):
     """Converged duct requests of both models, served batched in FP16
     deviations and plainly in FP32, against the steady series: per model
-    and edge the max-norm error over u_max and GRE_u, and |FP16 - FP32|."""
+    and edge the max-norm error over u_max and GRE_u, and |FP16 - FP32|.
+    odd: "magic" (the served ducts' odd rates, tied to s_nu) or "paper"
+    (Sec. 4's fixed s_q = 1.2, s_t = 0.98)."""
     from . import duct_series
     reqs = [{"id": i, "arrival": 0.0, "kind": "duct", "edge": L, "q": q, "steps": steps,
-             "stop_residual": None}
+             "stop_residual": None, "odd": odd}
             for i, (L, q) in enumerate((L, q) for L in edges for q in (14, 18))]
     series = lambda Y, Z, a, g, nu: duct_series.velocity(Y, Z, a, a, g, nu)  # noqa: E731
     b16, _ = serve_batched(reqs, "f16dev", keep_fields=True)
@@ -341,7 +438,7 @@ def duct_accuracy(edges=(32, 64, 96, 128, 160), steps=20000):
                       "f32_max": round(fm, 6), "f32_gre": round(fg, 6),
                       "f16_minus_f32_max": round(float(np.max(np.abs(h["u"] - f["u"])))
                                                  / DUCT_UMAX, 6)})
-    return {"steps": steps, "cases": cases,
+    return {"steps": steps, "odd_rates": odd, "cases": cases,
             "worst_f16dev_max": max(c["f16dev_max"] for c in cases),
             "worst_f16dev_gre": max(c["f16dev_gre"] for c in cases),
             "worst_f32_max": max(c["f32_max"] for c in cases),
