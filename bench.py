@@ -4,8 +4,13 @@ Workload (one "step" = one time step of the whole path: collision, streaming
 with bounce-back and the moving lid, plus the FP64 monitor every 1000
 steps): a 128^3 lid-driven cubic cavity, D3Q18, FP32 populations in SoA
 layout updated in place (AA pattern), lid speed 0.1, Re = 1000
-(nu = 0.0128).  Inputs are synthetic (the cavity starts at rest) and
-resident in HBM before timing starts.
+(nu = 0.0128).  Inputs are synthetic and resident in HBM before timing
+starts.  The cavity starts at rest, where every population is exactly zero
+(p0 = 0); --develop untimed steps (1000 by default, whatever --warmup is)
+let the lid's pressure waves cross the cube several times first, and the
+run stops unless fewer than 1 % of the populations are still exactly zero,
+so the timed steps stream developed flow, not zeros (which the Infinity
+Cache moves faster).
 
 Prints one JSON line.  value = MLUPS (million lattice-node updates per
 second); the roofline block reads the step kernels against the 8 TB/s HBM
@@ -27,6 +32,11 @@ METRIC = "MLUPS & % HBM roofline (D3Q18 FP32); batched serving p50/p99 latency v
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_step_d3q18_f32_aa_cavity128.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1503_03337_amd", "csrc", f)
                   for f in ("kernels.hip", "lattice.hpp", "kernels.hpp")]
+
+
+def note(msg):
+    """Progress of the run on stderr (stdout carries only the JSON line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def kernel_hash():
@@ -143,22 +153,59 @@ def mrt_vs_lbgk(torch, lbm, params, n=128, steps=2000):
     return out
 
 
-def storage_variants(torch, lbm, params, n=128, steps=2000):
-    """The headline cavity (128^3 D3Q18, AA, MRT) stored as FP16 deviations
-    (72 B per node and step) and as FP64 (288 B): MLUPS and algorithmic
-    GB/s of each."""
+def storage_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
+    """The headline cavity (128^3 D3Q18, AA, MRT) stored as FP64 (288 B per
+    node and step), FP32 (144 B) and FP16 deviations (72 B): MLUPS and
+    algorithmic GB/s of each over `steps` steps after `develop` untimed
+    ones, and the relative L2 error of u and p of the FP32 and FP16 runs
+    against the FP64 run at the same time level (develop + steps)."""
     cfg = params.cavity(18, n, 1000.0, lid=0.1)
-    out = {}
-    for storage, b in (("f16dev", 2), ("f64", 8)):
+    out, fields = {}, {}
+    for storage, b in (("f64", 8), ("f32", 4), ("f16dev", 2)):
         lat = lbm.Lattice(18, n, n, n, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"],
                           storage=storage, pattern="aa")
-        lat.step(1000)
+        lat.step(develop)
         wall, _ = time_steps(torch, lat, steps)
+        fields[storage] = lat.macros()
         lat.close()
         mlups = n ** 3 * steps / wall / 1e6
         out[storage] = {"MLUPS": round(mlups, 1),
                         "algorithmic_GBs": round(mlups * 1e6 * 2 * 18 * b / 1e9, 1)}
+    p64, u64 = fields["f64"]
+    for storage in ("f32", "f16dev"):
+        p, u = fields[storage]
+        out[storage]["rel_l2_u_vs_f64"] = float("%.3e" % rel_l2(u, u64))
+        out[storage]["rel_l2_p_vs_f64"] = float("%.3e" % rel_l2(p, p64))
+    out["time_level"] = develop + steps
     return out
+
+
+def zero_fraction(lat):
+    """Fraction of the lattice's physical populations that are exactly 0."""
+    import numpy as np
+    f = lat.get_f()
+    return float(np.count_nonzero(f == 0.0)) / f.size
+
+
+def monitor_cost(torch, lat, reps=10):
+    """Average device time of one FP64 monitor pass (mass, residual
+    partial sums, velocity snapshot and the final reduction), timed with
+    HIP events on the lattice's stream."""
+    stream = torch.cuda.current_stream()
+    lat.monitor()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        lat.monitor()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def cpu_baseline(target_seconds=15.0):
@@ -189,6 +236,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--develop", type=int, default=1000,
+                    help="untimed steps before --warmup that develop the flow from rest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--size", type=int, default=128)
@@ -203,15 +252,36 @@ def main():
     torch.cuda.set_device(0)
     n = args.size
     N = n ** 3
-    lat = cavity_lattice(lbm, params, n)
+    K = 1000  # monitor interval of the headline lattice
+    lat = cavity_lattice(lbm, params, n, monitor_every=K)
+    lat.step(args.develop)
+    zeros = zero_fraction(lat)
+    note("developed %d steps, %.4f %% of populations exactly zero" % (args.develop, 100 * zeros))
+    if zeros >= 0.01:
+        print("bench.py: %.1f %% of the populations are still exactly zero after %d "
+              "development steps; the timed steps would stream zeros (raise --develop)"
+              % (100.0 * zeros, args.develop), file=sys.stderr)
+        sys.exit(3)
     lat.step(args.warmup)
+    t_begin = lat.time
     wall, ev = time_steps(torch, lat, args.steps)
     mlups = N * args.steps / wall / 1e6
-    r = lat.residual() if lat.time >= 2000 else None
+    t_end = lat.time
+    # residual of the paper's steady-state criterion over the lag since the
+    # last monitor snapshot (the monitor runs every K steps inside lbm_step)
+    lat.monitor()
+    r_change, r_lag = lat.residual_change()
+    res = {"value": r_change, "lag_steps": r_lag, "per_step": r_change / r_lag,
+           "norm": "sum |u(t) - u(t - lag)| / sum |u(t)| over nodes and components"}
+    mon_us = monitor_cost(torch, lat)
     lat.close()
+    note("headline %.1f MLUPS over %d steps" % (mlups, args.steps))
+    # monitor passes inside the timed window (t a multiple of K)
+    n_mon = t_end // K - t_begin // K
+    step_us = (ev * 1e6 - n_mon * mon_us) / args.steps
 
     bytes_per_node = 2 * 18 * 4
-    achieved = bytes_per_node * N / (ev / args.steps) / 1e9
+    achieved = bytes_per_node * N / step_us / 1e3
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -219,15 +289,19 @@ def main():
 
     # the same kernels on a lattice larger than the 256 MB Infinity Cache
     big = cavity_lattice(lbm, params, 256, monitor_every=0)
-    big.step(20)
+    big.step(400)
     bsteps = 200
     bwall, bev = time_steps(torch, big, bsteps)
     big.close()
+    note("256^3 done")
     copy_gbs = copy_bandwidth(torch, lbm)
     copy_inplace_gbs = copy_bandwidth(torch, lbm, in_place=True)
     b256 = batch256(torch, lbm, params)
+    note("256-cavity batch done")
     collisions = mrt_vs_lbgk(torch, lbm, params)
+    note("collision comparison done")
     storages = storage_variants(torch, lbm, params)
+    note("storage variants done")
 
     out = {
         "metric": METRIC,
@@ -244,11 +318,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "D3Q18 MRT lid-driven cavity %d^3, Re=1000 (nu=%.4g), lid 0.1, "
                                "FP32 SoA populations, AA in-place streaming, FP64 monitor every "
-                               "1000 steps" % (n, 0.1 * n / 1000.0),
-                   "nodes": N, "bytes_per_node_step": bytes_per_node},
+                               "%d steps" % (n, 0.1 * n / 1000.0, K),
+                   "nodes": N, "bytes_per_node_step": bytes_per_node,
+                   "develop_steps": args.develop,
+                   "zero_populations_before_timing": round(zeros, 6),
+                   "timed_time_levels": [t_begin, t_end]},
         "roofline": roofline,
+        "step_kernel_us": round(step_us, 3),
+        "monitor": {"us_per_pass": round(mon_us, 2), "every_steps": K,
+                    "amortised_us_per_step": round(mon_us / K, 4),
+                    "passes_in_timed_window": n_mon},
         "hbm_roofline_fraction": round(mlups * 1e6 * bytes_per_node / (HBM_PEAK_GBS * 1e9), 4),
-        "residual_at_end": r,
+        "residual_at_end": res,
         "cavity256": {"MLUPS": round(256 ** 3 * bsteps / bwall / 1e6, 1),
                       "achieved_GBs": round(bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9, 1)},
         "copy_probe_GBs": round(copy_gbs, 1),
@@ -260,8 +341,10 @@ def main():
     if not args.no_serving:
         from paper_1503_03337_amd import serve
         out["serving"] = serve.bench_summary()
+        note("serving done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        note("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
