@@ -84,8 +84,9 @@ def copy_bandwidth(torch, lbm, nbytes=1 << 30, reps=20, in_place=False):
     """Bytes read + written per second by the plain copy kernel over nbytes
     (in place: source and destination are the same buffer, as in the AA
     step)."""
-    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    dst = src if in_place else torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    # non-zero data: zero pages move faster through the Infinity Cache
+    src = torch.randint(1, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = src if in_place else torch.randint(1, 256, (nbytes,), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     lbm.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, 2, stream.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -180,6 +181,23 @@ def storage_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
     return out
 
 
+def model_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
+    """The headline cavity (128^3, AA, FP32, MRT) with the 14- and the
+    26-velocity models (Sec. 3; the closing paragraph of Appendix B):
+    MLUPS and algorithmic GB/s at 2 q 4 bytes per node and step."""
+    out = {}
+    for q in (14, 26):
+        cfg = params.cavity(q, n, 1000.0, lid=0.1)
+        lat = lbm.Lattice(q, n, n, n, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"],
+                          storage="f32", pattern="aa")
+        lat.step(develop)
+        wall, ev = time_steps(torch, lat, steps)
+        lat.close()
+        out["d3q%d" % q] = {"MLUPS": round(n ** 3 * steps / wall / 1e6, 1),
+                            "algorithmic_GBs": round(2 * q * 4 * n ** 3 * steps / ev / 1e9, 1)}
+    return out
+
+
 def zero_fraction(lat):
     """Fraction of the lattice's physical populations that are exactly 0."""
     import numpy as np
@@ -241,6 +259,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline lattice and the copy reference only (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X; runs over several GPUs are not supported "
@@ -287,21 +307,28 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
 
-    # the same kernels on a lattice larger than the 256 MB Infinity Cache
-    big = cavity_lattice(lbm, params, 256, monitor_every=0)
-    big.step(400)
-    bsteps = 200
-    bwall, bev = time_steps(torch, big, bsteps)
-    big.close()
-    note("256^3 done")
     copy_gbs = copy_bandwidth(torch, lbm)
     copy_inplace_gbs = copy_bandwidth(torch, lbm, in_place=True)
-    b256 = batch256(torch, lbm, params)
-    note("256-cavity batch done")
-    collisions = mrt_vs_lbgk(torch, lbm, params)
-    note("collision comparison done")
-    storages = storage_variants(torch, lbm, params)
-    note("storage variants done")
+    extras = {}
+    if not args.headline_only:
+        # the same kernels on a lattice larger than the 256 MB Infinity Cache
+        big = cavity_lattice(lbm, params, 256, monitor_every=0)
+        big.step(400)
+        bsteps = 200
+        bwall, bev = time_steps(torch, big, bsteps)
+        big.close()
+        extras["cavity256"] = {
+            "MLUPS": round(256 ** 3 * bsteps / bwall / 1e6, 1),
+            "achieved_GBs": round(bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9, 1)}
+        note("256^3 done")
+        extras["batch256"] = batch256(torch, lbm, params)
+        note("256-cavity batch done")
+        extras["collision_cost"] = mrt_vs_lbgk(torch, lbm, params)
+        note("collision comparison done")
+        extras["storage_variants"] = storage_variants(torch, lbm, params)
+        note("storage variants done")
+        extras["model_variants"] = model_variants(torch, lbm, params)
+        note("model variants done")
 
     out = {
         "metric": METRIC,
@@ -330,19 +357,15 @@ def main():
                     "passes_in_timed_window": n_mon},
         "hbm_roofline_fraction": round(mlups * 1e6 * bytes_per_node / (HBM_PEAK_GBS * 1e9), 4),
         "residual_at_end": res,
-        "cavity256": {"MLUPS": round(256 ** 3 * bsteps / bwall / 1e6, 1),
-                      "achieved_GBs": round(bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9, 1)},
         "copy_probe_GBs": round(copy_gbs, 1),
         "copy_probe_inplace_GBs": round(copy_inplace_gbs, 1),
-        "batch256": b256,
-        "collision_cost": collisions,
-        "storage_variants": storages,
     }
-    if not args.no_serving:
+    out.update(extras)
+    if not args.no_serving and not args.headline_only:
         from paper_1503_03337_amd import serve
         out["serving"] = serve.bench_summary()
         note("serving done")
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.headline_only:
         out["cpu_baseline"] = cpu_baseline()
         note("cpu baseline done")
     print(json.dumps(out), flush=True)

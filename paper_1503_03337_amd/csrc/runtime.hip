@@ -1031,6 +1031,21 @@ bool member_flat(const Member& m) { return m.tx == 0 && m.ctx->N < (1u << 30); }
 // smaller ones one tile per workgroup, so that they keep enough workgroups.
 constexpr long long kBatchChunkMinTiles = 16384;
 
+// An FP32 member of at least this many nodes that is the only active
+// member of its (q, storage) class in a call takes its steps with the
+// single-lattice kernels (lbm_step's eager path: the same arithmetic and
+// bits), interleaved with the other classes' launches: for such a member
+// the class launch is the same work with the batch kernel's member lookup
+// on top (one 128^3 D3Q18 FP32 member: 44.5k MLUPS batched, 46.0k alone;
+// FP32 serving trace +0.7 % Poisson, +1.4 % saturated).  FP16 members keep
+// the class kernel, whose 256-node tiles measured faster for them (FP16
+// serving trace -0.7 % with solo members), and several large members of one
+// class keep sharing its launch (stepping every large member on its own
+// cost the saturated FP16 trace 6 %: 61.8k against 65.8k MLUPS).
+#ifndef LBM_BATCH_SOLO_NODES
+#define LBM_BATCH_SOLO_NODES (1ll << 18)
+#endif
+
 struct lbm_batch {
   hipStream_t stream = nullptr;
   std::vector<Member> members;
@@ -1159,19 +1174,54 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   if (!b || n < 0) return LBM_EINVAL;
   if (n == 0 || b->members.empty()) return LBM_OK;
   if (n > (1LL << 30)) return bfail(b, LBM_EINVAL, "n too large for one call");
-  // active members and their step counts for this call
-  std::vector<int> act;
-  long long nmax = 0;
+  // active members and their step counts for this call; a large member
+  // alone in its (q, storage) class steps on its own (solo)
+  std::vector<int> act, solo;
+  std::vector<long long> solo_k;
+  long long nmax = 0, solo_max = 0;
   size_t ftab_rows = 0, ntab_rows = 0;
+  auto model_storage = [&](size_t i) {
+    const lbm_ctx* c = b->members[i].ctx;
+    return 2 * (c->q == 14 ? 0 : c->q == 18 ? 1 : 2) + (c->spec.storage == LBM_F32 ? 0 : 1);
+  };
+  int per_class[6] = {};
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (std::min(n, b->members[i].remaining) > 0) ++per_class[model_storage(i)];
   for (size_t i = 0; i < b->members.size(); ++i) {
     const long long k = std::min(n, b->members[i].remaining);
     if (k <= 0) continue;
+    if ((long long)b->members[i].ctx->N >= (long long)LBM_BATCH_SOLO_NODES &&
+        per_class[model_storage(i)] == 1 && b->members[i].ctx->spec.storage == LBM_F32) {
+      solo.push_back((int)i);
+      solo_k.push_back(k);
+      solo_max = std::max(solo_max, k);
+      continue;
+    }
     act.push_back((int)i);
     nmax = std::max(nmax, k);
     if (b->members[i].ctx->forced) ftab_rows += (size_t)k;
     if (b->members[i].ctx->nee_count > 0) ntab_rows += (size_t)k;
   }
-  if (act.empty()) return LBM_OK;
+  auto solo_substep = [&](long long s) -> int {
+    for (size_t j = 0; j < solo.size(); ++j)
+      if (s < solo_k[j]) {
+        lbm_ctx* c = b->members[solo[j]].ctx;
+        const int rc = eager_step(c);
+        if (rc) return bfail(b, rc, c->err);
+      }
+    return LBM_OK;
+  };
+  auto solo_done = [&]() {
+    for (size_t j = 0; j < solo.size(); ++j) b->members[solo[j]].remaining -= solo_k[j];
+  };
+  if (act.empty()) {
+    for (long long s = 0; s < solo_max; ++s) {
+      const int rc = solo_substep(s);
+      if (rc) return rc;
+    }
+    solo_done();
+    return LBM_OK;
+  }
   // One specialised launch per (q, storage) class and step.  For n >= 2 the
   // members run in step with the AA parity of the first active member (one
   // out of step sits out the first substep of this call); for n == 1 the
@@ -1322,7 +1372,7 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   const int xcd = order_for(act_bytes, true);
   nmax = 0;
   for (int k = 0; k < NG; ++k) nmax = std::max(nmax, cls_steps[k]);
-  for (long long s = 0; s < nmax; ++s)
+  for (long long s = 0; s < std::max(nmax, solo_max); ++s) {
     for (int k = 0; k < NG; ++k) {
       if (cls_cnt[k] == 0 || s >= cls_steps[k]) continue;
       const int odd = (int)(((align ? parity : k / 6) + s) & 1);
@@ -1342,6 +1392,10 @@ int lbm_batch_step(lbm_batch* b, long long n) {
                                  b->d_members + cls_off[k], cls_cnt[k], b->d_ntab, (int)s,
                                  cls_nee[k], b->stream));
     }
+    const int rc = solo_substep(s);
+    if (rc) return rc;
+  }
+  solo_done();
   for (int j = 0; j < nm; ++j) {
     Member& m = b->members[act[j]];
     const long long k = std::min(n - ((align && m.ctx->phase != parity) ? 1 : 0), m.remaining);

@@ -13,6 +13,10 @@ fixed odd rates the wall moves with nu.  `odd_rates` returns that s_odd.
 import numpy as np
 
 S_C, S_E, S_Q, S_T, S_PI = 1.0, 1.19, 1.2, 0.98, 1.4
+# The 26-velocity model's energy-square moment (which the 14- and
+# 18-velocity models do not have) relaxes at the D3Q19-type value 1.4; its
+# second energy flux h takes s_q.
+S_EPS = 1.4
 
 # u_max of steady flow in a square duct of half-width a under body force g:
 # u_max = DUCT_UMAX_COEFF * g a^2 / nu (Sec. 4.1 series at the centre).
@@ -31,9 +35,11 @@ def odd_rates(sn, lam=MAGIC_LAMBDA):
     return 1.0 / (lam / (1.0 / sn - 0.5) + 0.5)
 
 
-def s_vec(q, nu=None, sn=None, s_e=S_E, s_q=S_Q, s_t=S_T, s_pi=S_PI, s_c=S_C):
-    """Relaxation rates in the moment order of Eq. (moment) (q = 14) or
-    Eq. (d3q18moment) (q = 18)."""
+def s_vec(q, nu=None, sn=None, s_e=S_E, s_q=S_Q, s_t=S_T, s_pi=S_PI, s_c=S_C, s_eps=S_EPS):
+    """Relaxation rates in the moment order of Eq. (moment) (q = 14),
+    Eq. (d3q18moment) (q = 18), or (P, e, eps, j_x, q_x, h_x, j_y, q_y, h_y,
+    j_z, q_z, h_z, 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz, pi_xy,
+    pi_yz, pi_xz, t_x, t_y, t_z, t_xyz) for the 26-velocity model."""
     if sn is None:
         sn = s_nu(nu)
     if q == 14:
@@ -41,7 +47,10 @@ def s_vec(q, nu=None, sn=None, s_e=S_E, s_q=S_Q, s_t=S_T, s_pi=S_PI, s_c=S_C):
     if q == 18:
         return np.array([s_c, s_e, s_c, s_q, s_c, s_q, s_c, s_q, sn, s_pi, sn, s_pi, sn, sn, sn,
                          s_t, s_t, s_t])
-    raise ValueError("q must be 14 or 18")
+    if q == 26:
+        return np.array([s_c, s_e, s_eps, s_c, s_q, s_q, s_c, s_q, s_q, s_c, s_q, s_q,
+                         sn, s_pi, sn, s_pi, sn, sn, sn, s_pi, s_pi, s_pi, s_t, s_t, s_t, s_t])
+    raise ValueError("q must be 14, 18 or 26")
 
 
 DUCT_FACES = ("periodic", "periodic", "wall", "wall", "wall", "wall")

@@ -267,8 +267,9 @@ def test_large_class_two_tiles_per_workgroup_bit_exact():
     member still equals its alone run (one tile per workgroup) bit for bit,
     including a ragged last chunk (odd tile counts)."""
     q, steps = 18, 5
-    # 256-node tiles of the automatic mapping: 5488 + 5586 + 5439 = 16513
-    dims = [(112, 112, 112), (112, 113, 113), (112, 112, 111)]
+    # members below the solo size (2^20 nodes), 256-node tiles of the
+    # automatic mapping: 3456 + 3529 + 3420 + 3456 + 3456 = 17317
+    dims = [(96, 96, 96), (96, 97, 97), (96, 96, 95), (95, 96, 97), (97, 95, 96)]
     s = svec(q, 1.6) + np.linspace(-0.02, 0.02, q)
 
     def make(k):
@@ -279,7 +280,7 @@ def test_large_class_two_tiles_per_workgroup_bit_exact():
         return lat
 
     alone = []
-    for k in range(3):
+    for k in range(len(dims)):
         lat = make(k)
         b = lbm.Batch(lat.stream)
         b.add(lat, steps)
@@ -287,7 +288,7 @@ def test_large_class_two_tiles_per_workgroup_bit_exact():
         b.close()
         alone.append(lat.macros()[1])
         lat.close()
-    lats = [make(k) for k in range(3)]
+    lats = [make(k) for k in range(len(dims))]
     b = lbm.Batch(lats[0].stream)
     for lat in lats:
         b.add(lat, steps)
@@ -348,16 +349,16 @@ def test_cavity_batch_256_full_size():
 def test_batch_beyond_384mb_equals_single_lattices():
     """A batch whose members hold more than 384 MB hands the XCDs chunks of
     workgroups in turn (another order than a smaller batch or a single
-    lattice uses).  The order changes no result: a D3Q18 member of 18.5k
-    tiles (the chunked kernel) and a ragged D3Q14 member (one tile per
-    workgroup), 464 MB together, equal single lattices bit for bit after an
-    even and an odd step and one more."""
-    members = [(18, (168, 168, 168), {"+z": (0.05, 0.0, 0.0)}),
-               (14, (130, 131, 129), {"+z": (0.0, 0.04, 0.0)})]
+    lattice uses).  The order changes no result: six D3Q18 members below the
+    solo size (17.7k tiles together: the chunked kernel) and a ragged D3Q14
+    member (one tile per workgroup), 445 MB together, equal single lattices
+    bit for bit after an even and an odd step and one more."""
+    members = [(18, (96, 96, 96 - k), {"+z": (0.05, 0.01 * k, 0.0)}) for k in range(6)]
+    members.append((14, (95, 97, 93), {"+z": (0.0, 0.04, 0.0)}))
     lats, singles = [], []
     for k, (q, dims, lid) in enumerate(members):
         for group in (lats, singles):
-            lat = lbm.Lattice(q, *dims, rates(q, k), faces=("wall",) * 6, wall_u=lid,
+            lat = lbm.Lattice(q, *dims, rates(q, k % 6), faces=("wall",) * 6, wall_u=lid,
                               storage="f32", pattern="aa")
             lat.set_f(inputs.random_populations(q, *dims, seed=640 + k))
             group.append(lat)
@@ -372,6 +373,39 @@ def test_batch_beyond_384mb_equals_single_lattices():
     for lat, single in zip(lats, singles):
         single.step(3)
         assert np.array_equal(lat.get_f(), single.get_f())
+    b.close()
+    for lat in lats + singles:
+        lat.close()
+
+
+def test_solo_and_classed_members_equal_single_lattices():
+    """Members of 2^20 nodes or more step on their own with the
+    single-lattice kernels, interleaved with the class launches of the small
+    members: a mix of large members (FP32 and FP16, D3Q18 and D3Q14, forced,
+    one out of AA parity) and small ones, stepped in uneven calls, equals
+    single lattices bit for bit."""
+    spec = [(18, (104, 104, 100), "f32", (1e-5, 0, 0)), (14, (101, 101, 103), "f16dev", (0, 0, 0)),
+            (18, (24, 20, 18), "f32", (0, 0, 0)), (14, (17, 23, 19), "f16dev", (2e-5, 0, 0)),
+            (18, (30, 9, 11), "f16dev", (0, 0, 0))]
+    lats, singles = [], []
+    for k, (q, dims, storage, F0) in enumerate(spec):
+        for group in (lats, singles):
+            lat = lbm.Lattice(q, *dims, rates(q, k), faces=("wall",) * 6,
+                              wall_u={"+z": (0.05, 0.0, 0.0)}, F0=F0, storage=storage,
+                              pattern="aa")
+            lat.set_f(inputs.random_populations(q, *dims, seed=660 + k))
+            if k in (1, 3):
+                lat.step(1)
+            group.append(lat)
+    assert lats[0].N >= 1 << 20 and lats[1].N >= 1 << 20
+    b = lbm.Batch(lats[0].stream)
+    for lat in lats:
+        b.add(lat, 40)
+    for n in (3, 1, 5, 2):
+        b.step(n)
+    for lat, single in zip(lats, singles):
+        single.step(lat.time - single.time)
+        assert np.array_equal(lat.get_f(), single.get_f()), (lat.q, lat.nx)
     b.close()
     for lat in lats + singles:
         lat.close()
