@@ -237,6 +237,21 @@ int lbm_macros(lbm_ctx* ctx, double* p, double* u);
 /* Same, into caller-owned device FP64 arrays; queued, does not wait. */
 int lbm_macros_device(lbm_ctx* ctx, double* p_dev, double* u_dev);
 
+/* For callers that cannot allocate (code between graph captures, tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_macros for the nodes
+ * [n0, n0 + count) without any allocation.  p[count] and u[3][count]
+ * (u_x, u_y, u_z, each count values) are caller-owned host FP64 arrays;
+ * either may be NULL.  The values equal those of lbm_macros at the same
+ * nodes bit for bit.  The call stages them in a static device array of the
+ * library (8 MiB per GPU, held until the process ends) instead of the device
+ * memory lbm_macros allocates, and calls no hipMalloc or hipFree.
+ * count <= LBM_NOALLOC_MAX_NODES (262,144), else LBM_EINVAL; a range outside
+ * the lattice is LBM_EINVAL.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (other host threads, other streams) race.
+ * Synchronises the stream. */
+#define LBM_NOALLOC_MAX_NODES 262144
+int lbm_macros_noalloc(lbm_ctx* ctx, long long n0, long long count, double* p, double* u);
+
 /* Velocity residual of the last monitor run:
  *   R = sum_n sum_k |u_k(n,t) - u_k(n,t-L)| / (L sum_n sum_k |u_k(n,t)|)
  * with L the steps since the previous snapshot (the steady-state criteria

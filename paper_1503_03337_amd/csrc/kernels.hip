@@ -895,30 +895,57 @@ __device__ __forceinline__ void macro_fp64(const C (&f)[Q], const C (&F)[3], dou
   uz = jz + 0.5 * (double)F[2];
 }
 
+// p and u (Eq. (hgl)) of node n in FP64.
 template <int Q, int ST, int PHASE>
-__global__ __launch_bounds__(256) void k_macros(LatticeArgs<typename Codec<ST>::C> A,
-                                                double* __restrict__ p, double* __restrict__ u) {
+__device__ __forceinline__ void node_macros(const LatticeArgs<typename Codec<ST>::C>& A,
+                                            long long n, double& p, double& ux, double& uy,
+                                            double& uz) {
   using CD = Codec<ST>;
   using C = typename CD::C;
   using L = Lattice<Q>;
-  const long long N = (long long)A.nx * A.ny * A.nz;
   const C F[3] = {A.F[0], A.F[1], A.F[2]};
+  int x, y, z;
+  node_xyz(n, A.nx, A.ny, x, y, z);
+  C f[Q];
+  read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), (unsigned)n, x, y, z,
+                                f);
+  double P;
+  macro_fp64<Q, C>(f, F, P, ux, uy, uz);
+  const double usq = ux * ux + uy * uy + uz * uz;
+  p = (P - 1.5 * L::w0 * usq) / (3.0 * (1.0 - L::w0));
+}
+
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_macros(LatticeArgs<typename Codec<ST>::C> A,
+                                                double* __restrict__ p, double* __restrict__ u) {
+  const long long N = (long long)A.nx * A.ny * A.nz;
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < N;
        n += (long long)gridDim.x * blockDim.x) {
-    int x, y, z;
-    node_xyz(n, A.nx, A.ny, x, y, z);
-    C f[Q];
-    read_node<Q, ST, PHASE, true>(A, static_cast<const typename CD::S*>(A.f), (unsigned)n, x, y, z,
-                                  f);
-    double P, ux, uy, uz;
-    macro_fp64<Q, C>(f, F, P, ux, uy, uz);
-    const double usq = ux * ux + uy * uy + uz * uz;
-    if (p) p[n] = (P - 1.5 * L::w0 * usq) / (3.0 * (1.0 - L::w0));
+    double pn, ux, uy, uz;
+    node_macros<Q, ST, PHASE>(A, n, pn, ux, uy, uz);
+    if (p) p[n] = pn;
     if (u) {
       u[n] = ux;
       u[N + n] = uy;
       u[2 * N + n] = uz;
     }
+  }
+}
+
+// Nodes [n0, n0 + count) into out[4 count]: p, then u_x, u_y, u_z, each
+// count values (the same arithmetic as k_macros).
+template <int Q, int ST, int PHASE>
+__global__ __launch_bounds__(256) void k_macros_range(LatticeArgs<typename Codec<ST>::C> A,
+                                                      long long n0, long long count,
+                                                      double* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    double pn, ux, uy, uz;
+    node_macros<Q, ST, PHASE>(A, n0 + i, pn, ux, uy, uz);
+    out[i] = pn;
+    out[count + i] = ux;
+    out[2 * count + i] = uy;
+    out[3 * count + i] = uz;
   }
 }
 
@@ -939,6 +966,29 @@ hipError_t launch_macros(int q, int storage, int phase, const void* args, double
                          hipStream_t s) {
   clear_stale_error();
   DISPATCH_QST(q, storage, return (macros_impl<Q_, ST_>(phase, args, p, u, s)));
+}
+
+template <int Q, int ST>
+static hipError_t macros_range_impl(int phase, const void* args, long long n0, long long count,
+                                    double* out, hipStream_t s) {
+  clear_stale_error();
+  using C = typename Codec<ST>::C;
+  const LatticeArgs<C>& A = *static_cast<const LatticeArgs<C>*>(args);
+  const long long N = (long long)A.nx * A.ny * A.nz;
+  if (n0 < 0 || count < 0 || n0 + count > N) return hipErrorInvalidValue;
+  if (count == 0) return hipSuccess;
+  const int nb = aux_blocks(count);
+  if (phase == 0)
+    hipLaunchKernelGGL((k_macros_range<Q, ST, 0>), dim3(nb), dim3(256), 0, s, A, n0, count, out);
+  else
+    hipLaunchKernelGGL((k_macros_range<Q, ST, 1>), dim3(nb), dim3(256), 0, s, A, n0, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_macros_range(int q, int storage, int phase, const void* args, long long n0,
+                               long long count, double* out, hipStream_t s) {
+  clear_stale_error();
+  DISPATCH_QST(q, storage, return (macros_range_impl<Q_, ST_>(phase, args, n0, count, out, s)));
 }
 
 // Deterministic block sum of three FP64 values: wavefront butterfly by

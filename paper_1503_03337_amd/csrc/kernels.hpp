@@ -95,6 +95,10 @@ hipError_t launch_init_eq(int q, int storage, const void* args, const double* p,
 // p[N], u[3][N] (FP64) of the current state with the force args.F.
 hipError_t launch_macros(int q, int storage, int phase, const void* args, double* p, double* u,
                          hipStream_t stream);
+// The same for nodes [n0, n0 + count) into out[4 count] (p, u_x, u_y, u_z,
+// each count values); hipErrorInvalidValue if the range leaves the lattice.
+hipError_t launch_macros_range(int q, int storage, int phase, const void* args, long long n0,
+                               long long count, double* out, hipStream_t stream);
 // Monitor pass 1: per-block FP64 partial sums of sum|u - snap|, sum|u|,
 // sum P into partial[3*nblocks]; refreshes snap (compute type) with u.
 // nblocks is returned through *nblocks_out (host computed).

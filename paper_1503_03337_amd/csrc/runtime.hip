@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -805,6 +806,93 @@ int lbm_macros(lbm_ctx* c, double* p, double* u) {
     HIPCHK(c, hipMemcpyAsync(p, tp.p, c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (u)
     HIPCHK(c, hipMemcpyAsync(u, tu.p, 3 * c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+// ---- the allocation-free macros call --------------------------------------
+// lbm_macros_noalloc stages p and u of a node range between the macros
+// kernel and the copies to the caller's host arrays in this file-scope
+// device array instead of memory it allocates: 8 MiB, p, u_x, u_y and u_z
+// of up to kNoallocNodes nodes.  Each GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not the device memory: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current and
+// kept in g_scratch_dev, and only that address is handed to kernels and
+// copies.
+namespace {
+constexpr long long kNoallocNodes = LBM_NOALLOC_MAX_NODES;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) double scratch[4 * kNoallocNodes];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up on first use).
+int scratch_address(lbm_ctx* c, double** out) {
+  if (c->device < 0 || c->device >= kMaxDevices)
+    return fail(c, LBM_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[c->device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(c, LBM_EDEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_dev[c->device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[c->device];
+  return LBM_OK;
+}
+
+// Makes the context's device current for a scope and restores the caller's.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceScope(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    int now = -1;
+    if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+  }
+};
+}  // namespace
+
+extern "C" {
+
+int lbm_macros_noalloc(lbm_ctx* c, long long n0, long long count, double* p, double* u) {
+  if (!c) return LBM_EINVAL;
+  if (n0 < 0 || count < 0 || n0 > (long long)c->N || count > (long long)c->N - n0)
+    return fail(c, LBM_EINVAL, "node range [n0, n0 + count) outside the lattice");
+  if (count > kNoallocNodes)
+    return fail(c, LBM_EINVAL,
+                "count " + std::to_string(count) + " exceeds the " +
+                    std::to_string(kNoallocNodes) +
+                    " nodes the static scratch of lbm_macros_noalloc holds (8 MiB)");
+  if (count == 0 || (!p && !u)) return LBM_OK;
+  DeviceScope scope(c->device);
+  if (scope.err != hipSuccess) return hip_fail(c, scope.err, "hipSetDevice");
+  double* s = nullptr;
+  int rc = scratch_address(c, &s);
+  if (rc) return rc;
+  set_force(*c, c->t);
+  const int phase = c->spec.pattern == LBM_AA ? c->phase : 0;
+  HIPCHK(c, launch_macros_range(c->q, c->spec.storage, phase, args_ptr(*c), n0, count, s,
+                                c->stream));
+  const size_t bytes = (size_t)count * sizeof(double);
+  if (p) HIPCHK(c, hipMemcpyAsync(p, s, bytes, hipMemcpyDeviceToHost, c->stream));
+  if (u)
+    for (int d = 0; d < 3; ++d)
+      HIPCHK(c, hipMemcpyAsync(u + (size_t)d * count, s + (size_t)(1 + d) * count, bytes,
+                               hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }

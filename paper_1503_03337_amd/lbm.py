@@ -27,6 +27,7 @@ PATTERN = {"ab": 0, "aa": 1}
 FACE_KIND = {"periodic": 0, "wall": 1, "symmetry": 2, "velocity": 3, "pressure": 4,
              "symmetry_node": 5}
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5
+NOALLOC_MAX_NODES = 262144  # LBM_NOALLOC_MAX_NODES
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
 
@@ -101,6 +102,7 @@ def lib():
             "lbm_step": (i, [vp, ll]),
             "lbm_macros": (i, [vp, dp, dp]),
             "lbm_macros_device": (i, [vp, vp, vp]),
+            "lbm_macros_noalloc": (i, [vp, ll, ll, dp, dp]),
             "lbm_residual": (i, [vp, dp]),
             "lbm_residual_change": (i, [vp, dp, C.POINTER(ll)]),
             "lbm_poll": (i, [vp]),
@@ -262,6 +264,16 @@ class Lattice:
         p = np.empty((self.nz, self.ny, self.nx))
         u = np.empty((3, self.nz, self.ny, self.nx))
         self._chk(lib().lbm_macros(self.h, _dptr(p), _dptr(u)), "lbm_macros")
+        return p, u
+
+    def macros_noalloc(self, n0, count):
+        """(p[count], u[3, count]) of nodes [n0, n0 + count) through
+        lbm_macros_noalloc (no allocation; count <= NOALLOC_MAX_NODES)."""
+        m = max(int(count), 0)  # the library rejects a negative count itself
+        p = np.empty(m)
+        u = np.empty((3, m))
+        self._chk(lib().lbm_macros_noalloc(self.h, int(n0), int(count), _dptr(p), _dptr(u)),
+                  "lbm_macros_noalloc")
         return p, u
 
     def macros_device(self, p_ptr, u_ptr):
