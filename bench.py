@@ -98,6 +98,34 @@ def copy_bandwidth(torch, lbm, nbytes=1 << 30, reps=20, in_place=False):
     return 2.0 * nbytes / sec / 1e9
 
 
+def pattern_ceiling(torch, lbm, edge, elem_bytes, q=18, reps=20):
+    """The AA step's access pattern without arithmetic (lbm_pattern_probe)
+    over an edge^3 lattice with the library's own population stride, on
+    non-zero data: microseconds of the even and of the odd pattern, and the
+    algorithmic GB/s of the pair (2 q b bytes per node and step), the
+    ceiling the step kernels' memory pattern allows, beside the plain
+    copy."""
+    N = edge ** 3
+    stride = (N + 63) // 64 * 64 + 1088
+    buf = torch.randint(1, 255, (q * stride * elem_bytes,), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for odd in (False, True):
+        lbm.pattern_probe(buf.data_ptr(), q, elem_bytes, (edge,) * 3, stride, odd, 2,
+                          stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lbm.pattern_probe(buf.data_ptr(), q, elem_bytes, (edge,) * 3, stride, odd, reps,
+                          stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["odd_us" if odd else "even_us"] = round(e0.elapsed_time(e1) * 1e3 / reps, 3)
+    del buf
+    mean_us = 0.5 * (out["even_us"] + out["odd_us"])
+    out["GBs"] = round(2.0 * q * elem_bytes * N / mean_us / 1e3, 1)
+    return out
+
+
 def batch256(torch, lbm, params, steps=100):
     """256 lid-driven cavities (edge U{24..96}, Re U[100,1000], D3Q14 or
     D3Q18 at random, seed 0), FP32 AA, advanced together: one launch per
@@ -158,7 +186,8 @@ def storage_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
     """The headline cavity (128^3 D3Q18, AA, MRT) stored as FP64 (288 B per
     node and step), FP32 (144 B) and FP16 deviations (72 B): MLUPS and
     algorithmic GB/s of each over `steps` steps after `develop` untimed
-    ones, and the relative L2 error of u and p of the FP32 and FP16 runs
+    ones, read against the ceiling of the access pattern in that element
+    size (lbm_swap_probe), and the relative L2 error of u and p of the FP32 and FP16 runs
     against the FP64 run at the same time level (develop + steps)."""
     cfg = params.cavity(18, n, 1000.0, lid=0.1)
     out, fields = {}, {}
@@ -166,12 +195,14 @@ def storage_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
         lat = lbm.Lattice(18, n, n, n, cfg["s_vec"], faces=cfg["faces"], wall_u=cfg["wall_u"],
                           storage=storage, pattern="aa")
         lat.step(develop)
-        wall, _ = time_steps(torch, lat, steps)
+        wall, ev = time_steps(torch, lat, steps)
         fields[storage] = lat.macros()
         lat.close()
-        mlups = n ** 3 * steps / wall / 1e6
-        out[storage] = {"MLUPS": round(mlups, 1),
-                        "algorithmic_GBs": round(mlups * 1e6 * 2 * 18 * b / 1e9, 1)}
+        gbs = 2 * 18 * b * n ** 3 * steps / ev / 1e9
+        ceil = pattern_ceiling(torch, lbm, n, b)
+        ceil["step_frac"] = round(gbs / ceil["GBs"], 4)
+        out[storage] = {"MLUPS": round(n ** 3 * steps / wall / 1e6, 1),
+                        "algorithmic_GBs": round(gbs, 1), "pattern_ceiling": ceil}
     p64, u64 = fields["f64"]
     for storage in ("f32", "f16dev"):
         p, u = fields[storage]
@@ -184,7 +215,8 @@ def storage_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
 def model_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
     """The headline cavity (128^3, AA, FP32, MRT) with the 14- and the
     26-velocity models (Sec. 3; the closing paragraph of Appendix B):
-    MLUPS and algorithmic GB/s at 2 q 4 bytes per node and step."""
+    MLUPS and algorithmic GB/s at 2 q 4 bytes per node and step, read
+    against the ceiling of the q-array access pattern (lbm_swap_probe)."""
     out = {}
     for q in (14, 26):
         cfg = params.cavity(q, n, 1000.0, lid=0.1)
@@ -193,8 +225,11 @@ def model_variants(torch, lbm, params, n=128, develop=1000, steps=2000):
         lat.step(develop)
         wall, ev = time_steps(torch, lat, steps)
         lat.close()
+        gbs = 2 * q * 4 * n ** 3 * steps / ev / 1e9
+        ceil = pattern_ceiling(torch, lbm, n, 4, q=q)
+        ceil["step_frac"] = round(gbs / ceil["GBs"], 4)
         out["d3q%d" % q] = {"MLUPS": round(n ** 3 * steps / wall / 1e6, 1),
-                            "algorithmic_GBs": round(2 * q * 4 * n ** 3 * steps / ev / 1e9, 1)}
+                            "algorithmic_GBs": round(gbs, 1), "pattern_ceiling": ceil}
     return out
 
 
@@ -289,9 +324,13 @@ def main():
     t_end = lat.time
     # residual of the paper's steady-state criterion over the lag since the
     # last monitor snapshot (the monitor runs every K steps inside lbm_step)
-    lat.monitor()
+    # (a run at t_end already happened inside lbm_step when K divides t_end;
+    # a second one at the same time level would have no lag)
+    if t_end % K:
+        lat.monitor()
     r_change, r_lag = lat.residual_change()
-    res = {"value": r_change, "lag_steps": r_lag, "per_step": r_change / r_lag,
+    res = {"value": r_change, "lag_steps": r_lag,
+           "per_step": r_change / r_lag if r_lag > 0 else None,
            "norm": "sum |u(t) - u(t - lag)| / sum |u(t)| over nodes and components"}
     mon_us = monitor_cost(torch, lat)
     lat.close()
@@ -309,6 +348,8 @@ def main():
 
     copy_gbs = copy_bandwidth(torch, lbm)
     copy_inplace_gbs = copy_bandwidth(torch, lbm, in_place=True)
+    ceiling = pattern_ceiling(torch, lbm, n, 4)
+    ceiling["step_frac"] = round(achieved / ceiling["GBs"], 4)
     extras = {}
     if not args.headline_only:
         # the same kernels on a lattice larger than the 256 MB Infinity Cache
@@ -317,9 +358,13 @@ def main():
         bsteps = 200
         bwall, bev = time_steps(torch, big, bsteps)
         big.close()
+        big_gbs = bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9
+        big_ceiling = pattern_ceiling(torch, lbm, 256, 4)
+        big_ceiling["step_frac"] = round(big_gbs / big_ceiling["GBs"], 4)
         extras["cavity256"] = {
             "MLUPS": round(256 ** 3 * bsteps / bwall / 1e6, 1),
-            "achieved_GBs": round(bytes_per_node * 256 ** 3 / (bev / bsteps) / 1e9, 1)}
+            "achieved_GBs": round(big_gbs, 1),
+            "pattern_ceiling": big_ceiling}
         note("256^3 done")
         extras["batch256"] = batch256(torch, lbm, params)
         note("256-cavity batch done")
@@ -359,6 +404,7 @@ def main():
         "residual_at_end": res,
         "copy_probe_GBs": round(copy_gbs, 1),
         "copy_probe_inplace_GBs": round(copy_inplace_gbs, 1),
+        "pattern_ceiling": ceiling,
     }
     out.update(extras)
     if not args.no_serving and not args.headline_only:

@@ -360,6 +360,19 @@ int lbm_batch_destroy(lbm_batch* b);
  * 384 MB, one contiguous range per XCD beyond.  Queued on stream. */
 int lbm_copy_probe(void* dst, const void* src, size_t bytes, int reps, void* stream);
 
+/* The memory pattern of an AA step without its arithmetic, `reps` times,
+ * over an nx x ny x nz lattice that is periodic on every axis: buf (device)
+ * holds q arrays (q = 14, 18 or 26) of elem_bytes-byte values (2, 4 or 8),
+ * `stride` >= nx ny nz elements apart, node n = x + nx (y + ny z).  odd = 0
+ * (the even step): every node moves its q values into the slots of the
+ * opposite velocities at the same node.  odd = 1 (the odd step): every node
+ * n reads slot abar at n - c_a and writes it into slot a at n + c_a.  Values
+ * move as raw bits, in the step kernels' thread mapping and workgroup order:
+ * the ceiling of their own access pattern, read beside the plain copy.
+ * LBM_EINVAL on bad arguments.  Queued on stream. */
+int lbm_pattern_probe(void* buf, int q, int elem_bytes, int nx, int ny, int nz,
+                      long long stride, int odd, int reps, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

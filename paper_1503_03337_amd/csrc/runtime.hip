@@ -19,6 +19,7 @@
 #include "../../include/lbm.h"
 #include "kernels.hpp"
 #include "lattice.hpp"
+#include "probes.hpp"
 
 using namespace lbm;
 
@@ -1082,6 +1083,23 @@ int lbm_destroy(lbm_ctx* c) {
     if (g) (void)hipGraphExecDestroy(g);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
+  return LBM_OK;
+}
+
+int lbm_pattern_probe(void* buf, int q, int elem_bytes, int nx, int ny, int nz,
+                      long long stride, int odd, int reps, void* stream) {
+  if (!buf || (q != 14 && q != 18 && q != 26) ||
+      (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) || nx < 1 || ny < 1 || nz < 1 ||
+      stride < (long long)nx * ny * nz || (odd != 0 && odd != 1) || reps < 0)
+    return LBM_EINVAL;
+  // the step kernels' workgroup order rule for this footprint (up to 384 MB:
+  // contiguous ranges per XCD; beyond, dispatch order here)
+  const size_t bytes = (size_t)q * (size_t)stride * (size_t)elem_bytes;
+  const int xcd = bytes <= (size_t)LBM_XCD_ORDER_MAX_BYTES ? 1 : 0;
+  for (int i = 0; i < reps; ++i)
+    if (launch_pattern_probe(buf, q, elem_bytes, nx, ny, nz, stride, odd, xcd,
+                             (hipStream_t)stream) != hipSuccess)
+      return LBM_EDEVICE;
   return LBM_OK;
 }
 

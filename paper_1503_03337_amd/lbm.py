@@ -129,6 +129,7 @@ def lib():
             "lbm_batch_last_error": (C.c_char_p, [vp]),
             "lbm_batch_destroy": (i, [vp]),
             "lbm_copy_probe": (i, [vp, vp, sz, i, vp]),
+            "lbm_pattern_probe": (i, [vp, i, i, i, i, i, ll, i, i, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -413,3 +414,11 @@ def copy_probe(dst_ptr, src_ptr, nbytes, reps=1, stream=None):
     rc = lib().lbm_copy_probe(dst_ptr, src_ptr, int(nbytes), int(reps), stream)
     if rc != 0:
         raise LbmError(rc, "lbm_copy_probe failed")
+
+
+def pattern_probe(buf_ptr, q, elem_bytes, shape, stride, odd=False, reps=1, stream=None):
+    nx, ny, nz = shape
+    rc = lib().lbm_pattern_probe(buf_ptr, int(q), int(elem_bytes), int(nx), int(ny), int(nz),
+                                 int(stride), int(bool(odd)), int(reps), stream)
+    if rc != 0:
+        raise LbmError(rc, "lbm_pattern_probe failed")

@@ -529,3 +529,48 @@ def test_copy_probe_copies_in_either_order(nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst, ref)
     assert torch.equal(src, ref)
+
+
+@pytest.mark.parametrize("q,elem", [(14, 4), (18, 2), (18, 4), (18, 8), (26, 4)])
+def test_pattern_probe_moves_the_data_of_both_aa_patterns(q, elem):
+    """The access-pattern reference moves data, not nothing, over a ragged
+    periodic lattice (partial tiles in x and y): the even pattern puts the
+    value of slot a into the slot of -c_a at the same node, the odd pattern
+    the value of slot abar at n - c_a into slot a at n + c_a; the pad beyond
+    the node count is untouched, and a second even pass restores the
+    buffer."""
+    import torch
+    c = velocities(q)
+    opp = [int(np.flatnonzero((c == -c[a]).all(axis=1))[0]) for a in range(q)]
+    nx, ny, nz = 70, 9, 5
+    nodes = nx * ny * nz
+    stride = (nodes + 63) // 64 * 64 + 1088
+    dt = {2: np.uint16, 4: np.uint32, 8: np.uint64}[elem]
+    gen = torch.Generator(device="cuda").manual_seed(q * 10 + elem)
+    buf = torch.randint(0, 256, (q * stride * elem,), dtype=torch.uint8, device="cuda",
+                        generator=gen)
+    ref = buf.clone()
+    a0 = ref.cpu().numpy().view(dt).reshape(q, stride)
+    stream = torch.cuda.current_stream().cuda_stream
+    lbm.pattern_probe(buf.data_ptr(), q, elem, (nx, ny, nz), stride, False, 1, stream)
+    torch.cuda.synchronize()
+    b_ = buf.cpu().numpy().view(dt).reshape(q, stride)
+    for a in range(q):
+        assert np.array_equal(b_[opp[a], :nodes], a0[a, :nodes]), a
+        assert np.array_equal(b_[a, nodes:], a0[a, nodes:]), a
+    lbm.pattern_probe(buf.data_ptr(), q, elem, (nx, ny, nz), stride, False, 1, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(buf, ref)
+    lbm.pattern_probe(buf.data_ptr(), q, elem, (nx, ny, nz), stride, True, 1, stream)
+    torch.cuda.synchronize()
+    b_ = buf.cpu().numpy().view(dt).reshape(q, stride)
+    for a in range(q):
+        # f'[a](m) = f[abar](m - 2 c_a), periodic; arrays indexed [z, y, x]
+        src_ = a0[opp[a], :nodes].reshape(nz, ny, nx)
+        want = np.roll(src_, shift=(2 * c[a][2], 2 * c[a][1], 2 * c[a][0]), axis=(0, 1, 2))
+        assert np.array_equal(b_[a, :nodes].reshape(nz, ny, nx), want), a
+        assert np.array_equal(b_[a, nodes:], a0[a, nodes:]), a
+    with pytest.raises(lbm.LbmError):
+        lbm.pattern_probe(buf.data_ptr(), q, 3, (nx, ny, nz), stride, False, 1, stream)
+    with pytest.raises(lbm.LbmError):
+        lbm.pattern_probe(buf.data_ptr(), q, elem, (nx, ny, nz), nodes - 1, False, 1, stream)
