@@ -1148,6 +1148,9 @@ constexpr long long kBatchChunkMinTiles = 16384;
 // serving trace -0.7 % with solo members), and several large members of one
 // class keep sharing its launch (stepping every large member on its own
 // cost the saturated FP16 trace 6 %: 61.8k against 65.8k MLUPS).
+// A member whose population buffer spans 4 GiB or more always steps on its
+// own: the class kernels address members with 32-bit offsets where that
+// pays (the odd step of FP16 and 26-velocity classes).
 #ifndef LBM_BATCH_SOLO_NODES
 #define LBM_BATCH_SOLO_NODES (1ll << 18)
 #endif
@@ -1296,8 +1299,10 @@ int lbm_batch_step(lbm_batch* b, long long n) {
   for (size_t i = 0; i < b->members.size(); ++i) {
     const long long k = std::min(n, b->members[i].remaining);
     if (k <= 0) continue;
-    if ((long long)b->members[i].ctx->N >= (long long)LBM_BATCH_SOLO_NODES &&
-        per_class[model_storage(i)] == 1 && b->members[i].ctx->spec.storage == LBM_F32) {
+    const lbm_ctx* mc = b->members[i].ctx;
+    const bool huge = population_bytes(mc->q, (size_t)mc->N, mc->spec.storage) > 0xffffffffull;
+    if (huge || ((long long)mc->N >= (long long)LBM_BATCH_SOLO_NODES &&
+                 per_class[model_storage(i)] == 1 && mc->spec.storage == LBM_F32)) {
       solo.push_back((int)i);
       solo_k.push_back(k);
       solo_max = std::max(solo_max, k);
