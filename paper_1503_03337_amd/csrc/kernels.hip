@@ -349,18 +349,15 @@ __device__ __forceinline__ Off32 make_off32(const LatticeArgs<C>& A, const Nbr& 
   return o;
 }
 
-// Lane and uniform offsets of the value population `a` reads (odd step:
-// gather from x - c_a, slot abar, or slot a of this node across an x wall;
-// dir = -1) or writes (push to x + c_a, slot a, or slot abar of this node
-// across an x wall; dir = +1), inner path.
+// Lane and uniform offsets of the value the odd step gathers as f_a on the
+// inner path: slot abar at x - c_a, or slot a of this node when x - c_a lies
+// beyond an x wall.
 template <int Q, typename S, typename C>
-__device__ __forceinline__ void aa_link32(const LatticeArgs<C>& A, const Nbr& b, const Off32& o,
-                                          int a, int dir, unsigned& vo, unsigned& so) {
+__device__ __forceinline__ void gather_off32(const LatticeArgs<C>& A, const Nbr& b, const Off32& o,
+                                             int a, unsigned& vo, unsigned& so) {
   using L = Lattice<Q>;
-  const int cx = dir * L::cx[a], cy = dir * L::cy[a], cz = dir * L::cz[a];
-  const int far = dir < 0 ? L::opp[a] : a;   // slot at the neighbour
-  const int here = dir < 0 ? a : L::opp[a];  // slot at this node across a wall
-  long long u = A.pofs[far];
+  const int cx = -L::cx[a], cy = -L::cy[a], cz = -L::cz[a];  // towards x - c_a
+  long long u = A.pofs[L::opp[a]];
   if (cy) u += (long long)b.oy[cy > 0] * (long long)sizeof(S);
   if (cz) u += (long long)b.oz[cz > 0] * (long long)sizeof(S);
   if (cx == 0) {
@@ -368,7 +365,7 @@ __device__ __forceinline__ void aa_link32(const LatticeArgs<C>& A, const Nbr& b,
     so = (unsigned)u + o.k;
   } else {
     const int k = cx > 0;
-    const unsigned u32 = (unsigned)u, d = (unsigned)A.pofs[here] - u32;
+    const unsigned u32 = (unsigned)u, d = (unsigned)A.pofs[a] - u32;
     vo = o.vx[k] + u32 + (o.wm[k] & d);
     so = 0u;
   }
@@ -390,16 +387,18 @@ __device__ __forceinline__ void read_odd32(const LatticeArgs<typename Codec<ST>:
   const Off32 o = make_off32<S>(A, b, n);
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
-    aa_link32<Q, S>(A, b, o, a, -1, vo[a], so[a]);
+    gather_off32<Q, S>(A, b, o, a, vo[a], so[a]);
     f[a] = CD::dec(BufIO<S>::load(r, vo[a], so[a]), A.base[wclass<Q>(a)], A.inv_scale);
   }
 }
 
 // Value population a leaves an inner-path node with: f_a - m bb_a, m = 1 on
 // the lane whose x + c_a is a wall and 0 elsewhere (only an x face can be a
-// wall there): one fused multiply-add with a per-lane 0/1 factor (m bb is
-// exact, so the result rounds like f_a - bb_a, and is f_a itself for m = 0)
-// instead of a select and a subtraction per population.
+// wall there): one fused multiply-add with a per-lane 0/1 factor instead of
+// a select and a subtraction per population.  m bb is exact, so the result
+// rounds like f_a - bb_a and equals f_a for m = 0 (a zero f_a may come out
+// with the other sign: the same value, so every later operation gives the
+// same result).
 template <int Q, typename C>
 __device__ __forceinline__ C leave_inner(const LatticeArgs<C>& A, const C (&mx)[2],
                                          const C (&f)[Q], int a) {
