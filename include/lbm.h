@@ -367,9 +367,11 @@ int lbm_copy_probe(void* dst, const void* src, size_t bytes, int reps, void* str
  * (the even step): every node moves its q values into the slots of the
  * opposite velocities at the same node.  odd = 1 (the odd step): every node
  * n reads slot abar at n - c_a and writes it into slot a at n + c_a.  Values
- * move as raw bits, in the step kernels' thread mapping and workgroup order:
- * the ceiling of their own access pattern, read beside the plain copy.
- * LBM_EINVAL on bad arguments.  Queued on stream. */
+ * move as raw bits, one thread per node in tiles of whole rows (256, 128 or
+ * 64 threads wide, 256 per workgroup), one contiguous range of workgroups
+ * per XCD up to 384 MB of populations and dispatch order beyond: the
+ * ceiling of the step kernels' own access pattern, read beside the plain
+ * copy.  LBM_EINVAL on bad arguments.  Queued on stream. */
 int lbm_pattern_probe(void* buf, int q, int elem_bytes, int nx, int ny, int nz,
                       long long stride, int odd, int reps, void* stream);
 
