@@ -23,6 +23,12 @@ CASES = {
     "cavity_f16_nearest_monitor": (18, (20, 18, 16), dict(
         faces=("wall",) * 6, wall_u={"+z": (0.08, 0, 0)}, storage="f16dev", pattern="aa",
         f16_rounding="nearest", monitor_every=50), True),
+    "cavity_f16_nearest_q14": (14, (22, 17, 15), dict(
+        faces=("wall",) * 6, wall_u={"+z": (0.06, 0.01, 0)}, storage="f16dev", pattern="aa",
+        f16_rounding="nearest"), True),
+    "periodic_yz_f16_nearest": (18, (19, 13, 11), dict(
+        faces=("wall", "wall") + ("periodic",) * 4, wall_u={"-x": (0, 0.04, 0.02)},
+        F0=(0, 1e-5, 0), storage="f16dev", pattern="aa", f16_rounding="nearest"), True),
     "pressure_duct_f64": (14, (21, 9, 9), dict(faces=NEE_FACES, face_p={"-x": 0.004, "+x": 0.0},
                                                storage="f64", pattern="aa"), True),
     "lbgk_symmetry_f32": (18, (16, 14, 12), dict(
