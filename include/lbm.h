@@ -1,7 +1,8 @@
 /*
  * lbm.h -- C ABI of the MI355X (gfx950) library for the incompressible
  * 14- and 18-velocity multiple-relaxation-time lattice Boltzmann models of
- * Zhang, Shi & Wang (arXiv 1503.03337).
+ * Zhang, Shi & Wang (arXiv 1503.03337), and the 26-velocity model built by
+ * the same construction (LBM_D3Q26 below).
  *
  * What one time step computes (per fluid node x, time level t -> t+1):
  *   - P = sum_a f_a, j = sum_a c_a f_a, u = j + F(t)/2 and
