@@ -463,6 +463,41 @@ def test_bgk_matches_oracle(q, storage, pattern, setup):
     lat.close()
 
 
+@pytest.mark.parametrize("q", (14, 18, 26))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("setup", ("duct_pulsatile", "cavity_lid"))
+def test_fp16dev_bgk_matches_oracle(q, pattern, setup):
+    """The LBGK collision on FP16 deviations (rounded to nearest) against the
+    oracle's MRT step with all rates 1/tau, under the rounding bounds of the
+    MRT test on the same storage: the even and the odd AA step each once."""
+    faces, wall_u, F0, FA, FT = SETUPS[setup]
+    dims = DIMS[0]
+    print("case q=%d %s %s" % (q, pattern, setup), flush=True)
+    s = np.full(q, 1.0 / 0.62)
+    lat = lbm.Lattice(q, *dims, s, faces=FACESETS[faces], wall_u=wall_u, F0=F0, FA=FA, FT=FT,
+                      storage="f16dev", pattern=pattern, collision="bgk",
+                      f16_rounding="nearest")
+    pr = R.problem(q, *dims, s, faces=FACESETS[faces], wall_u=wall_u, F0=F0, FA=FA, FT=FT)
+    lat.set_f(inputs.random_populations(q, *dims, seed=17))
+    f0 = lat.get_f()
+    eps = 2.0 ** -11
+    lat.step(1)
+    ref = R.run(pr, f0, 0, 1)
+    got = lat.get_f()
+    assert np.all(np.abs(got - ref) <= eps * np.abs(ref) + 1e-6 * np.max(np.abs(ref)))
+    k = 4
+    lat.step(k - 1)
+    ref = R.run(pr, ref, 1, k - 1)
+    assert rel_l2(lat.get_f(), ref) <= 2.0 * np.sqrt(k) * eps
+    p, u = lat.macros()
+    pr_, ur_ = R.macros(pr, ref, k)
+    fmax = np.max(np.abs(ref))
+    ncomp = 18 if q == 26 else 10
+    assert np.max(np.abs(u - ur_)) <= k * ncomp * eps * fmax
+    assert np.max(np.abs(p - pr_)) <= k * q * eps * fmax
+    lat.close()
+
+
 DEGENERATE = [(1, 1, 1), (1, 5, 4), (6, 1, 3), (5, 4, 1), (2, 2, 2), (257, 1, 2), (3, 2, 300)]
 DEGENERATE_FACES = {
     "periodic": ("periodic",) * 6,
