@@ -517,7 +517,11 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
 }
 
 // ---- one node, one step ------------------------------------------------------
-template <int Q, int ST, int MODE, bool FORCED, bool GEN, bool BGK = false>
+// RECOMP (general path): the push forms its addresses anew instead of
+// keeping the gather's 64-bit addresses live through the collision; the
+// coordinates pass through an empty asm statement, so the compiler cannot
+// reuse the gather's address arithmetic.
+template <int Q, int ST, int MODE, bool FORCED, bool GEN, bool BGK = false, bool RECOMP = false>
 __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::C>& A, int x, int y,
                                           int z) {
   using CD = Codec<ST>;
@@ -545,10 +549,12 @@ __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::
     collide<Q, C, FORCED>(f, r, F);
   }
   S* dst = static_cast<S*>(MODE == MODE_AB ? A.g : A.f);
+  unsigned nw = n;
+  if constexpr (RECOMP) asm volatile("" : "+v"(nw), "+v"(x), "+v"(y), "+v"(z));
   if (ST == ST_F16 && A.f16_sr)
-    write_node<Q, ST, MODE, GEN, true>(A, dst, n, x, y, z, f);
+    write_node<Q, ST, MODE, GEN, true>(A, dst, nw, x, y, z, f);
   else
-    write_node<Q, ST, MODE, GEN, false>(A, dst, n, x, y, z, f);
+    write_node<Q, ST, MODE, GEN, false>(A, dst, nw, x, y, z, f);
 }
 
 // The odd AA step of an inner-path node with 32-bit buffer offsets (the
@@ -622,6 +628,37 @@ __device__ __forceinline__ unsigned xcd_block(int order) {
   return ((i >> sh) << (sh + 3u)) + (xc << sh) + (i & ((1u << sh) - 1u));
 }
 
+// The kernel's own arguments re-read from the kernel-argument segment
+// behind an empty asm statement: scalar loads at the point of use that the
+// compiler cannot hoist into the kernel's entry.  (A kernel with one
+// by-value argument finds it at offset 0 of the segment.)
+template <typename C>
+__device__ __forceinline__ const LatticeArgs<C>& reread_args() {
+  typedef const __attribute__((address_space(4))) LatticeArgs<C>* kp_t;
+  kp_t p = (kp_t)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const LatticeArgs<C>*)p;
+}
+
+// Register budget of the odd AA step.  Its general path (y / z faces,
+// symmetry planes) holds every wall term and population offset and, left
+// to itself, sets the registers of the whole kernel: the compiler loads
+// all arguments at the kernel's entry, spills scalar registers into
+// vector-register lanes (reloaded on the inner path too) and keeps the
+// gather's 64-bit addresses live through the collision.  A lean general
+// path re-reads the arguments where it uses them and forms the push
+// addresses anew (RECOMP); the inner path then runs without reloads and
+// with fewer vector registers (the D3Q18 FP16 odd step: 62 instead of
+// 102, 7 waves per SIMD instead of 4), giving the same bits.  Measured per
+// kernel at 128^3 / 256^3: D3Q18 FP16 odd step -4.6 % / -8.4 %, D3Q14 FP16
+// -6 % / -7 %; at 128^3 D3Q26 FP16 -19 %, D3Q18 FP64 -2.3 %.  The FP32 odd
+// steps, and every even step, lost 1-3 % with it (more waves per SIMD than
+// HBM streaming wants) and keep the plain general path.
+template <int Q, int ST, int MODE>
+constexpr bool lean_general() {
+  return MODE == MODE_AA_ODD && ST != ST_F32;
+}
+
 template <int Q, int ST, int MODE, bool FORCED, bool BGK = false, bool O32 = false>
 __global__ __launch_bounds__(256) void k_step(LatticeArgs<typename Codec<ST>::C> A) {
   unsigned b = blockIdx.x;
@@ -640,7 +677,21 @@ __global__ __launch_bounds__(256) void k_step(LatticeArgs<typename Codec<ST>::C>
   const int x = bx * A.tx + (int)threadIdx.x;
   const int y = by * A.ty + (int)threadIdx.y;
   if (x >= A.nx || y >= A.ny) return;
-  node_step_any<Q, ST, MODE, FORCED, BGK, O32>(A, x, y, z);
+  if constexpr (lean_general<Q, ST, MODE>()) {
+    const bool inner =
+        (y > 0) & (y < A.ny - 1) & (z > 0) & (z < A.nz - 1) & ((A.sym & 3) == 0);
+    if (inner) {
+      if constexpr (O32)
+        node_step_odd32<Q, ST, FORCED, BGK>(A, x, y, z);
+      else
+        node_step<Q, ST, MODE, FORCED, false, BGK>(A, x, y, z);
+    } else {
+      node_step<Q, ST, MODE, FORCED, true, BGK, true>(reread_args<typename Codec<ST>::C>(), x, y,
+                                                      z);
+    }
+  } else {
+    node_step_any<Q, ST, MODE, FORCED, BGK, O32>(A, x, y, z);
+  }
 }
 
 // The odd AA step of the kernels whose vector instructions rival their
