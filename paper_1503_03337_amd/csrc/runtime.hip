@@ -1137,17 +1137,17 @@ bool member_flat(const Member& m) { return m.tx == 0 && m.ctx->N < (1u << 30); }
 // smaller ones one tile per workgroup, so that they keep enough workgroups.
 constexpr long long kBatchChunkMinTiles = 16384;
 
-// An FP32 member of at least this many nodes that is the only active
-// member of its (q, storage) class in a call takes its steps with the
-// single-lattice kernels (lbm_step's eager path: the same arithmetic and
-// bits), interleaved with the other classes' launches: for such a member
-// the class launch is the same work with the batch kernel's member lookup
-// on top (one 128^3 D3Q18 FP32 member: 44.5k MLUPS batched, 46.0k alone;
-// FP32 serving trace +0.7 % Poisson, +1.4 % saturated).  FP16 members keep
-// the class kernel, whose 256-node tiles measured faster for them (FP16
-// serving trace -0.7 % with solo members), and several large members of one
-// class keep sharing its launch (stepping every large member on its own
-// cost the saturated FP16 trace 6 %: 61.8k against 65.8k MLUPS).
+// A member of at least this many nodes that is the only active member of
+// its (q, storage) class in a call takes its steps with the single-lattice
+// kernels (lbm_step's eager path: the same arithmetic and bits),
+// interleaved with the other classes' launches: for such a member the class
+// launch is the same work with the batch kernel's member lookup on top (one
+// 128^3 D3Q18 FP32 member: 44.5k MLUPS batched, 46.0k alone; FP32 serving
+// trace +0.7 % Poisson, +1.4 % saturated), and an FP16 member would miss
+// the single-lattice odd step's lean general path (FP16 serving trace,
+// saturated: 72.0k against 68.7k MLUPS).  Several large members of one
+// class keep sharing its launch (stepping every large FP16 member on its
+// own measured 71.6k on the same trace).
 // A member whose population buffer spans 4 GiB or more always steps on its
 // own: the class kernels address members with 32-bit offsets where that
 // pays (the odd step of FP16 and 26-velocity classes).
@@ -1302,7 +1302,7 @@ int lbm_batch_step(lbm_batch* b, long long n) {
     const lbm_ctx* mc = b->members[i].ctx;
     const bool huge = population_bytes(mc->q, (size_t)mc->N, mc->spec.storage) > 0xffffffffull;
     if (huge || ((long long)mc->N >= (long long)LBM_BATCH_SOLO_NODES &&
-                 per_class[model_storage(i)] == 1 && mc->spec.storage == LBM_F32)) {
+                 per_class[model_storage(i)] == 1)) {
       solo.push_back((int)i);
       solo_k.push_back(k);
       solo_max = std::max(solo_max, k);
