@@ -27,7 +27,8 @@ def test_committed_profiles_match_the_kernel_sources():
     for name in ("kernel_trace_step_d3q18_f32_aa_cavity128.txt",
                  "pmc_step_d3q18_f32_aa_cavity128.txt",
                  "pmc_step_d3q18_storages_cavity128.txt",
-                 "kernel_trace_batch256_cavities.txt"):
+                 "kernel_trace_batch256_cavities.txt",
+                 "pmc_batch256_cavities.txt"):
         txt = open(os.path.join(ROOT, "profiles", name)).read()
         m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
         assert m and m.group(1) == h, name
