@@ -85,7 +85,8 @@ template <> struct Codec<ST_F32> {
 // FP16 deviation: stored h = fp16((f - base) 2^s).  Both directions are one
 // fused multiply-add: h 2^-s and f 2^s are exact products (2^s is a power of
 // two), so fma(h, 2^-s, base) rounds exactly like base + h 2^-s, and
-// fma(f, 2^s, -base 2^s) exactly like (f - base) 2^s.
+// fma(f, 2^s, -base 2^s) exactly like (f - base) 2^s.  (The step kernels
+// skip both: they compute on h itself, in deviation units; see step_dec.)
 // enc rounds to nearest.  enc_sr rounds stochastically with gfx950's
 // v_cvt_sr_f16_f32: the top 13 bits of the random word r are added below
 // the 10 mantissa bits FP16 keeps, then the rest is truncated, so a value
@@ -148,6 +149,38 @@ __device__ __forceinline__ typename Codec<ST>::S enc_any(const LatticeArgs<typen
                                                          unsigned h, int a) {
   return A.f16_sr ? enc_step<Q, ST, true>(A, v, slot, h, a)
                   : enc_step<Q, ST, false>(A, v, slot, h, a);
+}
+
+// Units of the step kernels.  FP16 lattices step in deviation units: the
+// collision runs on g = (f - base) 2^s, the stored value itself (the
+// deviation form of the collision is in lattice.hpp), so a stored value
+// converts to g exactly and the post-collision g is rounded once to FP16,
+// with no multiply-add on either side; the arithmetic works on the small
+// deviations instead of on base + deviation.  Their wall terms are held in
+// the same units (the host scales them by 2^s) and the body force is scaled
+// here.  FP32 and FP64 lattices step on f itself.  Everything else (set,
+// get, macros, monitors, the boundary pass) stays in f units.
+template <int ST>
+constexpr bool dev_units() {
+  return ST == ST_F16;
+}
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::C step_dec(typename Codec<ST>::S v) {
+  return static_cast<typename Codec<ST>::C>(v);
+}
+template <int ST, bool SR>
+__device__ __forceinline__ typename Codec<ST>::S step_enc(typename Codec<ST>::C v, unsigned h,
+                                                          int a) {
+  if constexpr (ST == ST_F16) {
+    if constexpr (SR) {
+      const unsigned r = pop_bits(h, a);
+      return __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, r), v, r, false)[0];
+    } else {
+      return static_cast<_Float16>(v);
+    }
+  } else {
+    return v;
+  }
 }
 
 // ---- neighbour offsets -----------------------------------------------------
@@ -388,7 +421,7 @@ __device__ __forceinline__ void read_odd32(const LatticeArgs<typename Codec<ST>:
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     gather_off32<Q, S>(A, b, o, a, vo[a], so[a]);
-    f[a] = CD::dec(BufIO<S>::load(r, vo[a], so[a]), A.base[wclass<Q>(a)], A.inv_scale);
+    f[a] = step_dec<ST>(BufIO<S>::load(r, vo[a], so[a]));
   }
 }
 
@@ -423,7 +456,7 @@ __device__ __forceinline__ void write_odd32(const LatticeArgs<typename Codec<ST>
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const int o = L::opp[a];
-    BufIO<S>::store(enc_step<Q, ST, SR>(A, leave_inner<Q>(A, mx, f, a), o, h, a), r, vo[o], so[o]);
+    BufIO<S>::store(step_enc<ST, SR>(leave_inner<Q>(A, mx, f, a), h, a), r, vo[o], so[o]);
   }
 }
 
@@ -434,7 +467,8 @@ __device__ __forceinline__ void write_odd32(const LatticeArgs<typename Codec<ST>
 // f*_abar(x) - 6 w_abar (c_abar . u_w).  When x - c_a lies beyond symmetry
 // planes only, the source node keeps x's coordinates along their normals and
 // the slot is the mirror image of abar.
-template <int Q, int ST, int PHASE, bool GEN, bool NT = false>
+// STEP: the values come out in the step kernels' units (dev_units).
+template <int Q, int ST, int PHASE, bool GEN, bool NT = false, bool STEP = false>
 __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::C>& A,
                                           const typename Codec<ST>::S* src, unsigned n, int x,
                                           int y, int z, typename Codec<ST>::C (&f)[Q]) {
@@ -445,8 +479,10 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
   const char* p0 = lane_ptr<S>(src, n);
   if (PHASE == 0) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a)
-      f[a] = CD::dec(pop_load<NT>((const S*)(p0 + A.pofs[a])), A.base[wclass<Q>(a)], A.inv_scale);
+    for (int a = 0; a < Q; ++a) {
+      const S v = pop_load<NT>((const S*)(p0 + A.pofs[a]));
+      f[a] = STEP ? step_dec<ST>(v) : CD::dec(v, A.base[wclass<Q>(a)], A.inv_scale);
+    }
   } else {
     const Nbr b = make_nbr<GEN>(A, x, y, z);
     // x - c_a: direction k = (-cx > 0) of the link taken from this node
@@ -462,7 +498,8 @@ __device__ __forceinline__ void read_node(const LatticeArgs<typename Codec<ST>::
       const char* nb = link_ptr<S, GEN>(A, b, p0, px, -L::cx[a], -L::cy[a], -L::cz[a], off,
                                         slot, o);
       const char* p = wall ? p0 + A.pofs[a] : nb;
-      f[a] = CD::dec(pop_load<NT>((const S*)p), A.base[wclass<Q>(a)], A.inv_scale);
+      const S v = pop_load<NT>((const S*)p);
+      f[a] = STEP ? step_dec<ST>(v) : CD::dec(v, A.base[wclass<Q>(a)], A.inv_scale);
     }
   }
 }
@@ -497,7 +534,7 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       bool wall;
       C term;
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
-      pop_store((S*)(p0 + A.pofs[o]), enc_step<Q, ST, SR>(A, f[a] - term, o, h, a));
+      pop_store((S*)(p0 + A.pofs[o]), step_enc<ST, SR>(f[a] - term, h, a));
     }
   } else {
     const char* const px[2] = {p0 + (long long)b.ox[0] * (long long)sizeof(S),
@@ -511,12 +548,39 @@ __device__ __forceinline__ void write_node(const LatticeArgs<typename Codec<ST>:
       link<Q, C>(b, A, a, L::cx[a], L::cy[a], L::cz[a], off, wall, term, slot);
       const char* nb = link_ptr<S, GEN>(A, b, p0, px, L::cx[a], L::cy[a], L::cz[a], off, slot, a);
       char* p = const_cast<char*>(wall ? p0 + A.pofs[o] : nb);
-      pop_store((S*)p, enc_step<Q, ST, SR>(A, f[a] - term, o, h, a));
+      pop_store((S*)p, step_enc<ST, SR>(f[a] - term, h, a));
     }
   }
 }
 
 // ---- one node, one step ------------------------------------------------------
+// The collision in the step kernels' units: MRT, or LBGK when BGK; in
+// deviation units the body force takes the factor 2^s and products take
+// 2^-s (lattice.hpp).
+template <int Q, int ST, bool FORCED, bool BGK>
+__device__ __forceinline__ void collide_step(const LatticeArgs<typename Codec<ST>::C>& A,
+                                             typename Codec<ST>::C (&f)[Q]) {
+  using C = typename Codec<ST>::C;
+  constexpr bool DEV = dev_units<ST>();
+  C F[3] = {A.F[0], A.F[1], A.F[2]};
+  if constexpr (DEV && FORCED) {
+    F[0] *= A.scale;
+    F[1] *= A.scale;
+    F[2] *= A.scale;
+  }
+  if constexpr (BGK) {
+    collide_bgk<Q, C, FORCED, DEV>(f, A.omega, A.hom, F, A.inv_scale);
+  } else {
+    Relax<C> r;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      r.sN[k] = A.sN[k];
+      r.hN[k] = A.hN[k];
+    }
+    collide<Q, C, FORCED, DEV>(f, r, F, A.inv_scale);
+  }
+}
+
 // RECOMP (general path): the push forms its addresses anew instead of
 // keeping the gather's 64-bit addresses live through the collision; the
 // coordinates pass through an empty asm statement, so the compiler cannot
@@ -530,24 +594,13 @@ __device__ __forceinline__ void node_step(const LatticeArgs<typename Codec<ST>::
   const unsigned n = (unsigned)x + (unsigned)A.nx * ((unsigned)y + (unsigned)A.ny * (unsigned)z);
   C f[Q];
   if (MODE == MODE_AB) {
-    read_node<Q, ST, 0, GEN, true>(A, static_cast<const S*>(A.f), n, x, y, z, f);
+    read_node<Q, ST, 0, GEN, true, true>(A, static_cast<const S*>(A.f), n, x, y, z, f);
   } else if (MODE == MODE_AA_EVEN) {
-    read_node<Q, ST, 0, GEN>(A, static_cast<const S*>(A.f), n, x, y, z, f);
+    read_node<Q, ST, 0, GEN, false, true>(A, static_cast<const S*>(A.f), n, x, y, z, f);
   } else {
-    read_node<Q, ST, 1, GEN>(A, static_cast<const S*>(A.f), n, x, y, z, f);
+    read_node<Q, ST, 1, GEN, false, true>(A, static_cast<const S*>(A.f), n, x, y, z, f);
   }
-  C F[3] = {A.F[0], A.F[1], A.F[2]};
-  if constexpr (BGK) {
-    collide_bgk<Q, C, FORCED>(f, A.omega, A.hom, F);
-  } else {
-    Relax<C> r;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      r.sN[k] = A.sN[k];
-      r.hN[k] = A.hN[k];
-    }
-    collide<Q, C, FORCED>(f, r, F);
-  }
+  collide_step<Q, ST, FORCED, BGK>(A, f);
   S* dst = static_cast<S*>(MODE == MODE_AB ? A.g : A.f);
   unsigned nw = n;
   if constexpr (RECOMP) asm volatile("" : "+v"(nw), "+v"(x), "+v"(y), "+v"(z));
@@ -567,18 +620,7 @@ __device__ __forceinline__ void node_step_odd32(const LatticeArgs<typename Codec
   C f[Q];
   unsigned vo[Q], so[Q];  // where each f_a was read
   read_odd32<Q, ST>(A, n, x, y, z, f, vo, so);
-  C F[3] = {A.F[0], A.F[1], A.F[2]};
-  if constexpr (BGK) {
-    collide_bgk<Q, C, FORCED>(f, A.omega, A.hom, F);
-  } else {
-    Relax<C> r;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      r.sN[k] = A.sN[k];
-      r.hN[k] = A.hN[k];
-    }
-    collide<Q, C, FORCED>(f, r, F);
-  }
+  collide_step<Q, ST, FORCED, BGK>(A, f);
   if (ST == ST_F16 && A.f16_sr)
     write_odd32<Q, ST, true>(A, n, x, y, z, f, vo, so);
   else

@@ -48,7 +48,8 @@ template <typename C> struct LatticeArgs {
                            // XCD; 2 chunks of 4 tiles per XCD in turn
   C sN[26], hN[26];        // s_k/N_k, (1 - s_k/2)/N_k
   C bb[26][3];             // 6 w_a (c_a . u_w) for link a leaving through
-                           // the x / y / z face it crosses
+                           // the x / y / z face it crosses (FP16 storage:
+                           // times 2^s, the step kernels' deviation units)
   C F[3];                  // body force at this step
   C base[3], base_s[3];    // FP16 deviation base 3 w_a p0 of the axis, edge
                            // and corner populations (|c_a|^2 = 1, 2, 3), and

@@ -103,6 +103,14 @@ __host__ __device__ constexpr int mirror(int a, int mask) {
 __device__ __forceinline__ float fma2(float k, float x, float y) { return __builtin_fmaf(k, x, y); }
 __device__ __forceinline__ double fma2(double k, double x, double y) { return __builtin_fma(k, x, y); }
 
+// Deviation units (DEV): the FP16 step kernels run the collision on
+// g = (f - f_rest) 2^s, the stored deviation itself, where f_rest is the
+// rest equilibrium at the reference pressure.  Every moment and equilibrium
+// term that is linear in f (or in p, j, F) carries the factor 2^s and
+// f_rest's share cancels exactly; a product of two such quantities (u u,
+// u F) would carry 2^2s, so one factor of each product is taken times
+// qs = 2^-s (exact: a power of two).  With DEV false qs is not used and the
+// arithmetic is the plain one.
 // Per-moment relaxation coefficients, pre-divided by the row norms:
 //   sN_k = s_k / N_k,   hN_k = (1 - s_k/2) / N_k,
 // so that d_k = D_k / N_k = sN_k (m_k - meq_k) - hN_k mF_k.
@@ -116,8 +124,9 @@ template <typename C> struct Relax {
 //   0 P, 1 e, 2 jx, 3 qx, 4 jy, 5 qy, 6 jz, 7 qz, 8 3pxx, 9 pww, 10 pxy,
 //   11 pyz, 12 pxz, 13 txyz.
 // ---------------------------------------------------------------------------
-template <typename C, bool FORCED>
-__device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C (&F)[3]) {
+template <typename C, bool FORCED, bool DEV = false>
+__device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C (&F)[3],
+                                          C qs = C(1)) {
   // forward: axis pairs
   const C ax = f[0] + f[1], dx = f[0] - f[1];
   const C ay = f[2] + f[3], dy = f[2] - f[3];
@@ -148,7 +157,8 @@ __device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C
     uy = fma2(C(0.5), F[1], uy);
     uz = fma2(C(0.5), F[2], uz);
   }
-  const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const C uxq = DEV ? ux * qs : ux, uyq = DEV ? uy * qs : uy, uzq = DEV ? uz * qs : uz;
+  const C uxx = uxq * ux, uyy = uyq * uy, uzz = uzq * uz;
   const C usq = uxx + uyy + uzz;
   const C p = (mP - usq * C(1.0 / 3.0)) * C(3.0 / 7.0);
 
@@ -163,14 +173,14 @@ __device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C
   C d7 = r.sN[7] * (qz + C(7.0 / 3.0) * uz);
   C d8 = r.sN[8] * (pxx3 - (C(3) * uxx - usq));
   C d9 = r.sN[9] * (pww - (uyy - uzz));
-  C d10 = r.sN[10] * (Kxy - ux * uy);
-  C d11 = r.sN[11] * (Kyz - uy * uz);
-  C d12 = r.sN[12] * (Kxz - ux * uz);
+  C d10 = r.sN[10] * (Kxy - uxq * uy);
+  C d11 = r.sN[11] * (Kyz - uyq * uz);
+  C d12 = r.sN[12] * (Kxz - uxq * uz);
   C d13 = r.sN[13] * Kxyz;
   if (FORCED) {
     // m_F = (d m_eq / d u) . F
     const C Fx = F[0], Fy = F[1], Fz = F[2];
-    const C w = ux * Fx + uy * Fy + uz * Fz;
+    const C w = uxq * Fx + uyq * Fy + uzq * Fz;
     d0 -= r.hN[0] * (C(2.0 / 3.0) * w);
     d1e -= r.hN[1] * (C(2) * w);
     d2 -= r.hN[2] * Fx;
@@ -179,11 +189,11 @@ __device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C
     d5 -= r.hN[5] * (C(-7.0 / 3.0) * Fy);
     d6 -= r.hN[6] * Fz;
     d7 -= r.hN[7] * (C(-7.0 / 3.0) * Fz);
-    d8 -= r.hN[8] * fma2(C(-2), w, C(6) * ux * Fx);
-    d9 -= r.hN[9] * (C(2) * (uy * Fy - uz * Fz));
-    d10 -= r.hN[10] * (ux * Fy + uy * Fx);
-    d11 -= r.hN[11] * (uy * Fz + uz * Fy);
-    d12 -= r.hN[12] * (ux * Fz + uz * Fx);
+    d8 -= r.hN[8] * fma2(C(-2), w, C(6) * uxq * Fx);
+    d9 -= r.hN[9] * (C(2) * (uyq * Fy - uzq * Fz));
+    d10 -= r.hN[10] * (uxq * Fy + uyq * Fx);
+    d11 -= r.hN[11] * (uyq * Fz + uzq * Fy);
+    d12 -= r.hN[12] * (uxq * Fz + uzq * Fx);
   }
 
   // back-transform f*_a = f_a - sum_k T_ka d_k, axis velocities
@@ -223,8 +233,9 @@ __device__ __forceinline__ void collide14(C (&f)[14], const Relax<C>& r, const C
 //   0 P, 1 e, 2 jx, 3 qx, 4 jy, 5 qy, 6 jz, 7 qz, 8 3pxx, 9 3pixx, 10 pww,
 //   11 piww, 12 pxy, 13 pyz, 14 pxz, 15 tx, 16 ty, 17 tz.
 // ---------------------------------------------------------------------------
-template <typename C, bool FORCED>
-__device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C (&F)[3]) {
+template <typename C, bool FORCED, bool DEV = false>
+__device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C (&F)[3],
+                                          C qs = C(1)) {
   const C ax = f[0] + f[1], dx = f[0] - f[1];
   const C ay = f[2] + f[3], dy = f[2] - f[3];
   const C az = f[4] + f[5], dz = f[4] - f[5];
@@ -267,7 +278,8 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
     uy = fma2(C(0.5), F[1], uy);
     uz = fma2(C(0.5), F[2], uz);
   }
-  const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const C uxq = DEV ? ux * qs : ux, uyq = DEV ? uy * qs : uy, uzq = DEV ? uz * qs : uz;
+  const C uxx = uxq * ux, uyy = uyq * uy, uzz = uzq * uz;
   const C usq = uxx + uyy + uzz;
   // Eq. (hgl) with w0 = 1/3: p = (P - |u|^2/2) / 2
   const C p = fma2(C(-0.5), usq, mP) * C(0.5);
@@ -285,17 +297,17 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
   C d9 = r.sN[9] * fma2(C(0.5), qxx, pixx3);
   C d10 = r.sN[10] * (pww - qww);
   C d11 = r.sN[11] * fma2(C(0.5), qww, piww);
-  C d12 = r.sN[12] * (XYxy - ux * uy);
-  C d13 = r.sN[13] * (YZyz - uy * uz);
-  C d14 = r.sN[14] * (XZxz - ux * uz);
+  C d12 = r.sN[12] * (XYxy - uxq * uy);
+  C d13 = r.sN[13] * (YZyz - uyq * uz);
+  C d14 = r.sN[14] * (XZxz - uxq * uz);
   C d15 = r.sN[15] * tx;
   C d16 = r.sN[16] * ty;
   C d17 = r.sN[17] * tz;
   if (FORCED) {
     const C Fx = F[0], Fy = F[1], Fz = F[2];
-    const C w = ux * Fx + uy * Fy + uz * Fz;
-    const C gxx = fma2(C(-2), w, C(6) * ux * Fx);
-    const C gww = uy * Fy - uz * Fz;
+    const C w = uxq * Fx + uyq * Fy + uzq * Fz;
+    const C gxx = fma2(C(-2), w, C(6) * uxq * Fx);
+    const C gww = uyq * Fy - uzq * Fz;
     d0 -= r.hN[0] * w;
     d1e -= r.hN[1] * w;
     d2 -= r.hN[2] * Fx;
@@ -308,9 +320,9 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
     d9 -= r.hN[9] * (C(-0.5) * gxx);
     d10 -= r.hN[10] * (C(2) * gww);
     d11 -= r.hN[11] * (-gww);
-    d12 -= r.hN[12] * (ux * Fy + uy * Fx);
-    d13 -= r.hN[13] * (uy * Fz + uz * Fy);
-    d14 -= r.hN[14] * (ux * Fz + uz * Fx);
+    d12 -= r.hN[12] * (uxq * Fy + uyq * Fx);
+    d13 -= r.hN[13] * (uyq * Fz + uzq * Fy);
+    d14 -= r.hN[14] * (uxq * Fz + uzq * Fx);
   }
 
   // back-transform, axis velocities (columns 1..6 of T)
@@ -375,8 +387,9 @@ __device__ __forceinline__ void collide18(C (&f)[18], const Relax<C>& r, const C
 // the D3Q27 weights): P 19p/9 + 4|u|^2/9, e -18p + |u|^2, eps 3p - |u|^2,
 // j u, q -2u, h u, the stresses as for 18 velocities with pi = -p, t 0.
 // ---------------------------------------------------------------------------
-template <typename C, bool FORCED>
-__device__ __forceinline__ void collide26(C (&f)[26], const Relax<C>& r, const C (&F)[3]) {
+template <typename C, bool FORCED, bool DEV = false>
+__device__ __forceinline__ void collide26(C (&f)[26], const Relax<C>& r, const C (&F)[3],
+                                          C qs = C(1)) {
   const C ax = f[0] + f[1], dx = f[0] - f[1];
   const C ay = f[2] + f[3], dy = f[2] - f[3];
   const C az = f[4] + f[5], dz = f[4] - f[5];
@@ -433,12 +446,13 @@ __device__ __forceinline__ void collide26(C (&f)[26], const Relax<C>& r, const C
     uy = fma2(C(0.5), F[1], uy);
     uz = fma2(C(0.5), F[2], uz);
   }
-  const C uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+  const C uxq = DEV ? ux * qs : ux, uyq = DEV ? uy * qs : uy, uzq = DEV ? uz * qs : uz;
+  const C uxx = uxq * ux, uyy = uyq * uy, uzz = uzq * uz;
   const C usq = uxx + uyy + uzz;
   // Eq. (hgl) with w0 = 8/27: p = 9/19 (P - 4/9 |u|^2)
   const C p = (mP - usq * C(4.0 / 9.0)) * C(9.0 / 19.0);
   const C qxx = C(3) * uxx - usq, qww = uyy - uzz;
-  const C uxy = ux * uy, uyz = uy * uz, uxz = ux * uz;
+  const C uxy = uxq * uy, uyz = uyq * uz, uxz = uxq * uz;
 
   C d0 = r.sN[0] * (mP - (C(19.0 / 9.0) * p + C(4.0 / 9.0) * usq));
   C d1 = r.sN[1] * (me - (usq - C(18) * p));
@@ -469,10 +483,10 @@ __device__ __forceinline__ void collide26(C (&f)[26], const Relax<C>& r, const C
   if (FORCED) {
     // m_F = (d m_eq / d u) . F
     const C Fx = F[0], Fy = F[1], Fz = F[2];
-    const C w = ux * Fx + uy * Fy + uz * Fz;
-    const C gxx = fma2(C(-2), w, C(6) * ux * Fx);
-    const C gww = C(2) * (uy * Fy - uz * Fz);
-    const C gxy = ux * Fy + uy * Fx, gyz = uy * Fz + uz * Fy, gxz = ux * Fz + uz * Fx;
+    const C w = uxq * Fx + uyq * Fy + uzq * Fz;
+    const C gxx = fma2(C(-2), w, C(6) * uxq * Fx);
+    const C gww = C(2) * (uyq * Fy - uzq * Fz);
+    const C gxy = uxq * Fy + uyq * Fx, gyz = uyq * Fz + uzq * Fy, gxz = uxq * Fz + uzq * Fx;
     d0 -= r.hN[0] * (C(8.0 / 9.0) * w);
     d1 -= r.hN[1] * (C(2) * w);
     d2 -= r.hN[2] * (C(-2) * w);
@@ -578,8 +592,9 @@ __device__ __forceinline__ void collide26(C (&f)[26], const Relax<C>& r, const C
 // velocity-space form of the moment force (no transform needed).
 // omega = 1/tau, hom = 1 - omega/2.
 // ---------------------------------------------------------------------------
-template <int Q, typename C, bool FORCED>
-__device__ __forceinline__ void collide_bgk(C (&f)[Q], C omega, C hom, const C (&F)[3]) {
+template <int Q, typename C, bool FORCED, bool DEV = false>
+__device__ __forceinline__ void collide_bgk(C (&f)[Q], C omega, C hom, const C (&F)[3],
+                                            C qs = C(1)) {
   using L = Lattice<Q>;
   C P = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
@@ -595,10 +610,13 @@ __device__ __forceinline__ void collide_bgk(C (&f)[Q], C omega, C hom, const C (
     uy = fma2(C(0.5), F[1], uy);
     uz = fma2(C(0.5), F[2], uz);
   }
-  const C usq = ux * ux + uy * uy + uz * uz;
+  const C uxq = DEV ? ux * qs : ux, uyq = DEV ? uy * qs : uy, uzq = DEV ? uz * qs : uz;
+  const C usq = uxq * ux + uyq * uy + uzq * uz;
   // Eq. (hgl): p = (P - 3/2 w0 |u|^2) / (3 (1 - w0))
   const C p = (P - C(1.5 * L::w0) * usq) * C(1.0 / (3.0 * (1.0 - L::w0)));
-  const C uF = FORCED ? ux * F[0] + uy * F[1] + uz * F[2] : C(0);
+  const C uF = FORCED ? uxq * F[0] + uyq * F[1] + uzq * F[2] : C(0);
+  // (c.u)^2 and (c.u)(c.F) take 2^-s through their constant factor
+  const C k45 = DEV ? C(4.5) * qs : C(4.5), k9 = DEV ? C(9) * qs : C(9);
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     const C w = C(weight<Q>(a));
@@ -606,21 +624,22 @@ __device__ __forceinline__ void collide_bgk(C (&f)[Q], C omega, C hom, const C (
     if (L::cx[a]) { cu += L::cx[a] > 0 ? ux : -ux; if (FORCED) cF += L::cx[a] > 0 ? F[0] : -F[0]; }
     if (L::cy[a]) { cu += L::cy[a] > 0 ? uy : -uy; if (FORCED) cF += L::cy[a] > 0 ? F[1] : -F[1]; }
     if (L::cz[a]) { cu += L::cz[a] > 0 ? uz : -uz; if (FORCED) cF += L::cz[a] > 0 ? F[2] : -F[2]; }
-    const C feq = w * (C(3) * p + C(3) * cu + C(4.5) * cu * cu - C(1.5) * usq);
+    const C feq = w * (C(3) * p + C(3) * cu + k45 * cu * cu - C(1.5) * usq);
     C fa = f[a] - omega * (f[a] - feq);
-    if (FORCED) fa += hom * (w * (C(3) * cF + C(9) * cu * cF - C(3) * uF));
+    if (FORCED) fa += hom * (w * (C(3) * cF + k9 * cu * cF - C(3) * uF));
     f[a] = fa;
   }
 }
 
-template <int Q, typename C, bool FORCED>
-__device__ __forceinline__ void collide(C (&f)[Q], const Relax<C>& r, const C (&F)[3]) {
+template <int Q, typename C, bool FORCED, bool DEV = false>
+__device__ __forceinline__ void collide(C (&f)[Q], const Relax<C>& r, const C (&F)[3],
+                                        C qs = C(1)) {
   if constexpr (Q == 14)
-    collide14<C, FORCED>(f, r, F);
+    collide14<C, FORCED, DEV>(f, r, F, qs);
   else if constexpr (Q == 18)
-    collide18<C, FORCED>(f, r, F);
+    collide18<C, FORCED, DEV>(f, r, F, qs);
   else
-    collide26<C, FORCED>(f, r, F);
+    collide26<C, FORCED, DEV>(f, r, F, qs);
 }
 
 }  // namespace lbm

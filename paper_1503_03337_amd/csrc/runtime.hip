@@ -300,9 +300,12 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
     A.sN[k] = (C)(c.s[k] / Nk[k]);
     A.hN[k] = (C)((1.0 - 0.5 * c.s[k]) / Nk[k]);
   }
+  const double sc = std::ldexp(1.0, c.spec.f16_scale_log2);
   // Wall term of population a leaving through the face its d-component
   // points at: 6 w_a (c_a . u_w), computed as the FP64 oracle of the paper
-  // would (w_a times 6, times the dot product).
+  // would (w_a times 6, times the dot product); for FP16 storage in the
+  // step kernels' deviation units (times 2^s, exact).
+  const double bb_units = c.spec.storage == LBM_F16DEV ? sc : 1.0;
   for (int a = 0; a < c.q; ++a) {
     const int comp[3] = {cx[a], cy[a], cz[a]};
     for (int d = 0; d < 3; ++d) {
@@ -311,10 +314,9 @@ void fill_args(const lbm_ctx& c, LatticeArgs<C>& A) {
       const int face = 2 * d + (comp[d] > 0 ? 1 : 0);
       const double* uw = c.spec.wall_u[face];
       const double cu = cx[a] * uw[0] + cy[a] * uw[1] + cz[a] * uw[2];
-      A.bb[a][d] = (C)(6.0 * w[a] * cu);
+      A.bb[a][d] = (C)(6.0 * w[a] * cu * bb_units);
     }
   }
-  const double sc = std::ldexp(1.0, c.spec.f16_scale_log2);
   A.scale = (C)sc;
   A.inv_scale = (C)(1.0 / sc);
   // one base per weight class (|c_a|^2 = 1, 2, 3); classes a model lacks
