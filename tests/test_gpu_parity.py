@@ -182,6 +182,42 @@ def test_fp16dev_with_background_pressure_matches_oracle(q):
     assert err <= 2.0 * np.sqrt(k) * 2.0 ** -10, err
     lat.close()
 
+@pytest.mark.parametrize("q", (14, 18, 26))
+@pytest.mark.parametrize("pattern", ("ab", "aa"))
+@pytest.mark.parametrize("setup", ("duct_pulsatile", "symmix_force", "cavity_lid"))
+@pytest.mark.parametrize("collision", ("mrt", "bgk"))
+def test_fp16_steps_are_invariant_under_the_deviation_scale(q, pattern, setup, collision):
+    """FP16 lattices store h = (f - 3 w p0) 2^s and step on h itself: every
+    term of the collision linear in f, p, j or F carries 2^s and each product
+    of two such quantities one factor 2^-s.  Raising s by one doubles every
+    stored value exactly (while values stay in FP16's normal range; both
+    rounding modes round the same mantissa), so the decoded populations
+    after even and odd steps are the same bits for s = 12 and s = 13, with a
+    background pressure, walls, moving walls, symmetry planes and a body
+    force.  A term with a wrong power of the scale breaks this."""
+    faces, wall_u, F0, FA, FT = SETUPS[setup]
+    dims = DIMS[0]
+    p0 = 0.3
+    s = rates(q) if collision == "mrt" else np.full(q, 1.0 / 0.62)
+    _, w, _, _, _, _ = R.lattice(q)
+    f0 = (3.0 * w * p0).reshape(q, 1, 1, 1) + inputs.random_populations(q, *dims, seed=21)
+    for rounding in ("nearest", "stochastic"):
+        got = []
+        for log2 in (12, 13):
+            lat = lbm.Lattice(q, *dims, s, faces=FACESETS[faces], wall_u=wall_u, F0=F0, FA=FA,
+                              FT=FT, storage="f16dev", pattern=pattern, collision=collision,
+                              f16_rounding=rounding, p0=p0, f16_scale_log2=log2)
+            lat.set_f(f0)
+            start = lat.get_f()
+            lat.step(5)
+            got.append((start, lat.get_f()))
+            lat.close()
+        assert np.array_equal(got[0][0], got[1][0]), rounding
+        assert np.all(np.isfinite(got[0][1]))
+        assert not np.array_equal(got[0][1], got[0][0])
+        assert np.array_equal(got[0][1], got[1][1]), rounding
+
+
 def test_fp16_stochastic_rounding_is_unbiased():
     """Zero rates in a periodic box only move values, and a body force adds
     a Guo source of ~3e-7 per population and step -- far below half an FP16
