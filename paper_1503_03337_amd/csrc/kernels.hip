@@ -321,9 +321,9 @@ __device__ __forceinline__ const char* link_ptr(const LatticeArgs<C>& A, const N
 // uniform part of a c_x = 0 link is shifted up by K = (nx ny + nx) b and the
 // lane part down by K, which the inner path (y, z >= 1) allows.  The
 // gather of f_a and the push of f*_abar touch the same value (the AA
-// property), so the push reuses the gather's offsets.  The resource covers
-// exactly the population buffer, so an offset past it would read 0 and
-// drop the store rather than touch other memory.
+// property), so the push reuses the gather's offsets.  The resource spans
+// exactly the population buffer, and every offset formed here lies inside
+// it.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 template <int Q, typename C>
 __device__ __forceinline__ rsrc_t pop_rsrc(const LatticeArgs<C>& A, const void* buf) {
@@ -694,8 +694,9 @@ __device__ __forceinline__ const LatticeArgs<C>& reread_args() {
 // 102, 7 waves per SIMD instead of 4), giving the same bits.  Measured per
 // kernel at 128^3 / 256^3: D3Q18 FP16 odd step -4.6 % / -8.4 %, D3Q14 FP16
 // -6 % / -7 %; at 128^3 D3Q26 FP16 -19 %, D3Q18 FP64 -2.3 %.  The FP32 odd
-// steps, and every even step, lost 1-3 % with it (more waves per SIMD than
-// HBM streaming wants) and keep the plain general path.
+// steps lost 1.4-2.8 % with it (6 waves per SIMD instead of 4: more than
+// HBM streaming wants there) and keep the plain general path, as do the
+// even steps, which moved by -0.8 % to +1.5 %.
 template <int Q, int ST, int MODE>
 constexpr bool lean_general() {
   return MODE == MODE_AA_ODD && ST != ST_F32;
