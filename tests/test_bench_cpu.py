@@ -28,7 +28,8 @@ def test_committed_profiles_match_the_kernel_sources():
                  "pmc_step_d3q18_f32_aa_cavity128.txt",
                  "pmc_step_d3q18_storages_cavity128.txt",
                  "kernel_trace_batch256_cavities.txt",
-                 "pmc_batch256_cavities.txt"):
+                 "pmc_batch256_cavities.txt",
+                 "pmc_step_d3q18_f32_aa_cavity256.txt"):
         txt = open(os.path.join(ROOT, "profiles", name)).read()
         m = re.search(r"kernel_source_hash:\s*(\w+)", txt)
         assert m and m.group(1) == h, name
