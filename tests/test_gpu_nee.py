@@ -84,8 +84,9 @@ def test_fp64_matches_oracle(q, pattern, setup):
 @pytest.mark.parametrize("q", (14, 18, 26))
 @pytest.mark.parametrize("storage", ("f32", "f16dev"))
 @pytest.mark.parametrize("setup", sorted(SETUPS))
-def test_reduced_storage_matches_oracle(q, storage, setup):
-    lat, pr = make(q, setup, storage, "aa")
+@pytest.mark.parametrize("pattern", ("aa", "ab"))
+def test_reduced_storage_matches_oracle(q, storage, setup, pattern):
+    lat, pr = make(q, setup, storage, pattern)
     f = lat.get_f()
     lat.step(6)
     f = R.run(pr, f, 0, 6)
