@@ -99,7 +99,7 @@ def test_reduced_storage_matches_oracle(q, storage, setup, pattern):
 
 
 @pytest.mark.parametrize("q", (14, 18, 26))
-@pytest.mark.parametrize("storage", ("f64", "f32"))
+@pytest.mark.parametrize("storage", ("f64", "f32", "f16dev"))
 @pytest.mark.parametrize("setup", sorted(SETUPS))
 def test_aa_equals_ab_bit_exact(q, storage, setup):
     out = {}
