@@ -48,10 +48,16 @@ PLAIN_CHUNK = 1000    # steps per lbm_step call of the plain server
 DUCT_UMAX = 0.05      # centre-line speed of duct requests
 CAVITY_RE = 400.0     # cavity Reynolds number at lid speed 0.1
 DUCT_EFOLD = 1500.0   # slowest duct mode decays within this many steps
-# A D3Q18 FP32 lattice of 2^21 nodes (128^3, 2 x 18 x 4 B moved per node
-# and step) runs the single-lattice kernel at full bandwidth on MI355X;
-# batches are filled up to that many bytes moved per step.
-SATURATION_BYTES = (1 << 21) * 144
+# Batches are filled up to what a D3Q18 FP32 lattice of 2^19 nodes (80^3,
+# 2 x 18 x 4 B moved per node and step) moves per step.  A large member
+# alone in its class steps with the single-lattice kernels at full speed,
+# so a larger cap only shares the GPU between large requests: on the
+# serving trace a cap of 2^21 nodes' bytes (128^3) left the batched FP16
+# server 1.4 % behind the plain one saturated, with a Poisson p99 of 1.27
+# against 0.82 s, and the batched FP32 server's Poisson p99 at 2.09 against
+# 2.00 s; with 2^19 both servers match or beat the plain ones in throughput,
+# p50 and p99 (2^20 lies between).
+SATURATION_BYTES = (1 << 19) * 144
 STORAGE_BYTES = {"f32": 4, "f16dev": 2, "f64": 8}
 
 
