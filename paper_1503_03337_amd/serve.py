@@ -3,8 +3,8 @@
 Requests (duct or cavity solves of uneven sizes, D3Q14 or D3Q18, a step
 budget or a stop at a velocity residual) arrive over time.  Two servers:
 
-  plain    one request at a time, in arrival order, FP32 storage, the
-           single-lattice kernel (lbm_step)
+  plain    one request at a time, in arrival order, the single-lattice
+           kernel (lbm_step); storage FP32 or FP16 deviations
   batched  continuous batching: arrived requests are admitted, in arrival
            order, while their HBM footprint (lbm_footprint_bytes) fits the
            budget and the admitted lattices move fewer bytes per step than
