@@ -47,6 +47,26 @@ def test_mix_equals_alone_and_budget_respected(storage):
         assert np.array_equal(a["u"], m["u"]), req
 
 
+def test_traffic_cap_runs_large_requests_one_after_another():
+    """Admission stops while the admitted lattices move SATURATION_BYTES per
+    step, and a request always enters an empty batch: two requests that each
+    move more than that run one after the other, two quanta each, and three
+    small ones that together stay under it share two quanta (6 quanta in
+    all).  Without the cap all five share the same two quanta."""
+    def req(i, edge):
+        return {"id": i, "arrival": 0.0, "kind": "cavity", "edge": edge, "q": 18, "steps": 200,
+                "stop_residual": None}
+    big = [req(0, 96), req(1, 96)]
+    small = [req(10, 24), req(11, 24), req(12, 24)]
+    assert all(serve.step_bytes(r, "f32") > serve.SATURATION_BYTES for r in big)
+    assert sum(serve.step_bytes(r, "f32") for r in small) <= serve.SATURATION_BYTES
+    for cap, quanta in ((serve.SATURATION_BYTES, 6), (None, 2)):
+        recs, info = serve.serve_batched(big + small, "f32", quantum=100, max_active_bytes=cap)
+        assert len(recs) == 5 and all(r["status"] == "ok" and r["steps_done"] == 200
+                                      for r in recs)
+        assert info["step_launches"] == 100 * quanta, (cap, info)
+
+
 def test_plain_and_batched_agree():
     trace = [r for r in small_trace() if r["stop_residual"] is None][:4]
     plain, _ = serve.serve_plain(trace, "f32", keep_fields=True)
